@@ -1,0 +1,381 @@
+"""Seeded synthetic plasma states for the Vlasov translation path.
+
+This module only *samples* initial distribution functions f(x, v) on a sparse
+velocity mesh; it contains no part of the translation method (no
+reconstruction, flux, remap or pruning step).  Both the CPU oracle and the HIP
+library are fed from here, so neither side's arithmetic ever produces the
+other's input.
+
+State layout (local cells only, x fastest):
+  offsets : int64[ncell + 1]   CSR row pointers, in blocks
+  ids     : int32[nblocks]     global velocity-block ids, ascending per cell
+  f       : float64[nblocks*64] 64 phase-space densities per block [s^3 m^-6]
+
+Velocity mesh: nblk[d] blocks of 4 cells per axis; block id
+  b = bx + nblk_x * (by + nblk_y * bz); lane within a block l = ix + 4 iy + 16 iz;
+cell-centre velocity v_d(j) = vmin_d + (j + 1/2) dv_d with j = 4 b_d + i_d.
+
+The workloads follow the physical setups of the paper's scaling runs
+(Section 4.1: T = 1e5 K, n = 1e6 m^-3, V_x = 100 km/s, dv = 30 km/s; Section
+2.2: cold solar wind at -750 km/s, dv = 40 km/s), since the paper's own
+datasets are not public.  Initial f is a point sample of the analytic
+distribution at velocity-cell centres times (1 + 0.01 u), u uniform in
+[-1, 1) from a counter-based SplitMix64 stream (Steele, Lea & Flood 2014)
+keyed by (seed, local cell, block id, lane), so any sub-box can be regenerated
+independently of list selection and of the order of generation.
+"""
+from __future__ import annotations
+
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+
+M_P = 1.67262192e-27  # proton mass [kg]
+K_B = 1.380649e-23    # Boltzmann constant [J/K]
+
+VL_F64, VL_F32, VL_BF16 = 0, 1, 2
+
+
+@dataclass
+class Workload:
+    name: str
+    n: tuple            # local spatial cells per axis
+    dx: tuple           # spatial cell size [m]
+    nblk: tuple         # velocity blocks per axis
+    vmin: tuple         # lower velocity-mesh edge [m/s]
+    dv: tuple           # velocity cell size [m/s]
+    dt: float           # time step [s]
+    steps: int
+    sparse_min: float   # block-content threshold [s^3 m^-6]; <= 0: no pruning
+    vbuffer: int        # velocity-space buffer: 0, 6 (face) or 26 neighbours
+    storage: int = VL_F64
+    order: tuple = (0, 1, 2)
+    offsets: np.ndarray = field(default=None, repr=False)
+    ids: np.ndarray = field(default=None, repr=False)
+    f: np.ndarray = field(default=None, repr=False)
+    seed: int = 0
+    # the physical fields the state was sampled from (per local cell)
+    fields: dict = field(default=None, repr=False)
+
+    @property
+    def ncell(self):
+        return int(np.prod(self.n))
+
+    @property
+    def nblocks(self):
+        return int(self.offsets[-1])
+
+    @property
+    def nv(self):
+        return tuple(4 * b for b in self.nblk)
+
+    def max_courant(self):
+        c = 0.0
+        for d in range(3):
+            nv = 4 * self.nblk[d]
+            vlo = self.vmin[d] + 0.5 * self.dv[d]
+            vhi = self.vmin[d] + (nv - 0.5) * self.dv[d]
+            c = max(c, max(abs(vlo), abs(vhi)) * self.dt / self.dx[d])
+        return c
+
+
+# --------------------------------------------------------------------------
+# counter-based uniform noise (SplitMix64 finaliser over a counter)
+# --------------------------------------------------------------------------
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(counter: np.ndarray, seed: int) -> np.ndarray:
+    """SplitMix64 output for state = seed + (counter + 1) * golden (uint64)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (counter.astype(np.uint64) + np.uint64(1)) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform_pm1(counter: np.ndarray, seed: int) -> np.ndarray:
+    """u in [-1, 1) with 53 random bits."""
+    z = splitmix64(counter, seed)
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 / 9007199254740992.0) - 1.0
+
+
+# --------------------------------------------------------------------------
+# smooth periodic fields from seeded sine sums
+# --------------------------------------------------------------------------
+def sine_sum_field(rng, n, nmodes=3):
+    """Normalised periodic field s(x) in [-1, 1] on an n-box of cell centres.
+
+    s = sum_m a_m sin(2 pi k_m . x / L + phi_m) / sum_m |a_m|,
+    k_m integer in {-2..2}^3 \\ {0}."""
+    ks = []
+    while len(ks) < nmodes:
+        k = rng.integers(-2, 3, size=3)
+        if np.any(k != 0):
+            ks.append(k)
+    amps = rng.uniform(0.5, 1.0, size=nmodes)
+    phases = rng.uniform(0.0, 2 * np.pi, size=nmodes)
+    x = [(np.arange(n[d]) + 0.5) / n[d] for d in range(3)]
+    X, Y, Z = np.meshgrid(x[0], x[1], x[2], indexing="ij")
+    s = np.zeros(X.shape)
+    for k, a, ph in zip(ks, amps, phases):
+        s += a * np.sin(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+    s /= amps.sum()
+    # (x, y, z) -> flat x-fastest
+    return np.ascontiguousarray(s.transpose(2, 1, 0)).reshape(-1)
+
+
+# --------------------------------------------------------------------------
+# velocity-space geometry
+# --------------------------------------------------------------------------
+def _lane_offsets():
+    l = np.arange(64)
+    return np.stack([l & 3, (l >> 2) & 3, l >> 4], axis=1)  # (64, 3)
+
+
+def _block_coords(nblk):
+    b = np.arange(nblk[0] * nblk[1] * nblk[2])
+    return np.stack([b % nblk[0], (b // nblk[0]) % nblk[1], b // (nblk[0] * nblk[1])], axis=1)
+
+
+def _dilate(mask, nblk, vbuffer):
+    """mask: (m, NB) bool -> dilation by the face (6) or full (26) neighbours."""
+    if vbuffer == 0:
+        return mask.copy()
+    m = mask.shape[0]
+    g = mask.reshape(m, nblk[2], nblk[1], nblk[0])
+    out = g.copy()
+    if vbuffer == 6:
+        shifts = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    else:
+        shifts = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)
+                  if (a, b, c) != (0, 0, 0)]
+    for sx, sy, sz in shifts:
+        src = [slice(None)] * 4
+        dst = [slice(None)] * 4
+        for ax, s in ((3, sx), (2, sy), (1, sz)):
+            if s == 1:
+                dst[ax] = slice(1, None)
+                src[ax] = slice(0, -1)
+            elif s == -1:
+                dst[ax] = slice(0, -1)
+                src[ax] = slice(1, None)
+        out[tuple(dst)] |= g[tuple(src)]
+    return out.reshape(m, -1)
+
+
+# --------------------------------------------------------------------------
+# distribution-function models (per cell parameters)
+# --------------------------------------------------------------------------
+# A cell model is a list of components; each component is a dict with keys
+# n (m^-3), V (3,), Tpar, Tperp (K), bhat (3,). Isotropic Maxwellian:
+# Tpar == Tperp.
+
+def _component_f(v, comp):
+    """Analytic (bi-)Maxwellian at velocities v (..., 3)."""
+    n, V, Tpa, Tpe, bh = comp["n"], comp["V"], comp["Tpar"], comp["Tperp"], comp["bhat"]
+    u = v - V
+    upar = u @ bh
+    u2 = np.einsum("...i,...i->...", u, u)
+    uperp2 = np.maximum(u2 - upar * upar, 0.0)
+    spa = K_B * Tpa / M_P
+    spe = K_B * Tpe / M_P
+    norm = n / ((2.0 * np.pi) ** 1.5 * spe * math.sqrt(spa))
+    return norm * np.exp(-0.5 * upar * upar / spa - 0.5 * uperp2 / spe)
+
+
+def _component_radius2(comp, thresh):
+    """Squared radius (in the component's metric bound) beyond which
+    1.01 * f_component < thresh / 2 (so a sum of <= 2 components stays
+    below thresh)."""
+    spa = K_B * comp["Tpar"] / M_P
+    spe = K_B * comp["Tperp"] / M_P
+    peak = comp["n"] / ((2.0 * np.pi) ** 1.5 * spe * math.sqrt(spa))
+    r = 1.01 * peak / (0.5 * thresh)
+    if r <= 1.0:
+        return -1.0
+    return 2.0 * max(spa, spe) * math.log(r)
+
+
+def sample_cells(models, nblk, vmin, dv, sparse_min, vbuffer, seed, cell_ids,
+                 threads=None, batch=64):
+    """Sample the sparse state of the cells whose global local-cell indices are
+    `cell_ids` (x-fastest numbering of the full local box).
+
+    Block selection: with sparse_min > 0, a block is kept if any of its 64
+    sampled values is >= sparse_min, plus the `vbuffer` velocity neighbours of
+    such blocks (clipped to the mesh).  With sparse_min <= 0 every block is
+    kept (dense mesh)."""
+    NB = nblk[0] * nblk[1] * nblk[2]
+    bc = _block_coords(nblk)                      # (NB, 3)
+    lo = _lane_offsets()                          # (64, 3)
+    vmin = np.asarray(vmin, dtype=np.float64)
+    dv = np.asarray(dv, dtype=np.float64)
+    # block centre-grid bounding boxes of the velocity-cell centres
+    blo = vmin + (4 * bc + 0.5) * dv
+    bhi = vmin + (4 * bc + 3.5) * dv
+
+    def values(cells_global, cell_models, pairs_cell, pairs_blk):
+        v = vmin + (4 * bc[pairs_blk][:, None, :] + lo[None, :, :] + 0.5) * dv  # (p,64,3)
+        fv = np.zeros(v.shape[:2])
+        # group pairs by cell to evaluate the cell's components
+        for ci in np.unique(pairs_cell):
+            sel = np.nonzero(pairs_cell == ci)[0]
+            acc = np.zeros((sel.size, 64))
+            for comp in cell_models[ci]:
+                acc += _component_f(v[sel], comp)
+            fv[sel] = acc
+        counter = ((cells_global[pairs_cell].astype(np.int64) * NB + pairs_blk)[:, None] * 64
+                   + np.arange(64)[None, :])
+        u = uniform_pm1(counter, seed)
+        return fv * (1.0 + 0.01 * u)
+
+    def do_batch(cb):
+        cells_global = np.asarray(cb, dtype=np.int64)
+        m = cells_global.size
+        cell_models = [models(int(c)) for c in cells_global]
+        if sparse_min > 0:
+            cand = np.zeros((m, NB), dtype=bool)
+            for i, comps in enumerate(cell_models):
+                for comp in comps:
+                    r2 = _component_radius2(comp, sparse_min)
+                    if r2 < 0:
+                        continue
+                    near = np.clip(comp["V"], blo, bhi)
+                    d2 = np.sum((near - comp["V"]) ** 2, axis=1)
+                    cand[i] |= d2 <= r2
+            union = cand | _dilate(cand, nblk, vbuffer)
+            pc, pb = np.nonzero(union)
+            fv = values(cells_global, cell_models, pc, pb)
+            content = np.zeros((m, NB), dtype=bool)
+            content[pc, pb] = np.any(fv >= sparse_min, axis=1)
+            final = _dilate(content, nblk, vbuffer)
+            keep = final[pc, pb]
+            pc, pb, fv = pc[keep], pb[keep], fv[keep]
+        else:
+            pc = np.repeat(np.arange(m), NB)
+            pb = np.tile(np.arange(NB), m)
+            fv = values(cells_global, cell_models, pc, pb)
+        counts = np.bincount(pc, minlength=m)
+        return counts, pb.astype(np.int32), fv.reshape(-1)
+
+    cell_ids = np.asarray(cell_ids, dtype=np.int64)
+    batches = [cell_ids[i:i + batch] for i in range(0, cell_ids.size, batch)]
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    if threads > 1 and len(batches) > 1:
+        with ThreadPoolExecutor(threads) as ex:
+            res = list(ex.map(do_batch, batches))
+    else:
+        res = [do_batch(b) for b in batches]
+    counts = np.concatenate([r[0] for r in res]) if res else np.zeros(0, np.int64)
+    offsets = np.zeros(cell_ids.size + 1, dtype=np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    ids = np.concatenate([r[1] for r in res]) if res else np.zeros(0, np.int32)
+    f = np.concatenate([r[2] for r in res]) if res else np.zeros(0)
+    return offsets, ids, f
+
+
+def _iso(n, V, T):
+    return {"n": float(n), "V": np.asarray(V, dtype=np.float64), "Tpar": float(T),
+            "Tperp": float(T), "bhat": np.array([1.0, 0.0, 0.0])}
+
+
+# --------------------------------------------------------------------------
+# the named workloads
+# --------------------------------------------------------------------------
+def maxwellian_small(seed=21451, n=(8, 8, 8)):
+    """Dense FP64 case: 8^3 periodic cells, dx = 300 km, 16^3 velocity cells
+    (4^3 blocks) with dv = 40 km/s over +-320 km/s; proton Maxwellian with
+    n(x) = 1e6 (1 + 0.2 sin(2 pi x / L)), V = (100, 0, 0) km/s, T = 1e5 K,
+    +-1 % noise; dt such that the largest cell-centre |v| dt / dx = 0.5."""
+    dx = (300e3,) * 3
+    nblk = (4, 4, 4)
+    dv = (40e3,) * 3
+    vmin = (-320e3,) * 3
+    Lx = n[0] * dx[0]
+
+    def model(c):
+        ix = c % n[0]
+        xc = (ix + 0.5) * dx[0]
+        return [_iso(1e6 * (1.0 + 0.2 * math.sin(2 * math.pi * xc / Lx)), (100e3, 0.0, 0.0), 1e5)]
+
+    offsets, ids, f = sample_cells(model, nblk, vmin, dv, 0.0, 0, seed,
+                                   np.arange(n[0] * n[1] * n[2]))
+    vmax_c = 320e3 - 20e3
+    dt = 0.5 * dx[0] / vmax_c
+    return Workload("maxwellian-8x8x8-dense-v16", tuple(n), dx, nblk, vmin, dv, dt, 10,
+                    0.0, 0, VL_F64, (0, 1, 2), offsets, ids, f, seed)
+
+
+def _smooth_fields(seed, n):
+    rng = np.random.default_rng(seed)
+    sn = sine_sum_field(rng, n)
+    sT = sine_sum_field(rng, n)
+    sV = [sine_sum_field(rng, n) for _ in range(3)]
+    dens = 1e6 + 3e6 * 0.5 * (sn + 1.0)
+    temp = 10.0 ** (5.0 + 0.5 * (sT + 1.0))
+    vel = np.stack([600e3 / math.sqrt(3.0) * s for s in sV], axis=1)
+    return dens, temp, vel
+
+
+def maxwellian_sparse(seed=21452, n=(64, 64, 32), cells=None, threads=None, steps=20,
+                      storage=VL_F64):
+    """Sparse FP64 case on a coalesced-ghost partition: 64 x 64 x 32 periodic
+    cells, dx = 300 km, 100^3 velocity cells (25^3 blocks), dv = 30 km/s over
+    +-1500 km/s; one Maxwellian per cell with n in [1e6, 4e6] m^-3 (linear),
+    T in [1e5, 1e6] K (logarithmic) and each bulk-velocity component in
+    +-600/sqrt(3) km/s, all from seeded periodic sine sums; blocks kept where
+    max f >= 1e-15 s^3 m^-6 plus the 6 face-neighbour blocks.  dt gives a
+    largest Courant number of 1/2 (dx = 300 km is assumed; only v dt / dx
+    matters).  `cells` restricts sampling to a subset of local cells (the
+    fields stay those of the full box)."""
+    dx = (300e3,) * 3
+    nblk = (25, 25, 25)
+    dv = (30e3,) * 3
+    vmin = (-1500e3,) * 3
+    dens, temp, vel = _smooth_fields(seed, n)
+
+    def model(c):
+        return [_iso(dens[c], vel[c], temp[c])]
+
+    if cells is None:
+        cells = np.arange(n[0] * n[1] * n[2])
+    offsets, ids, f = sample_cells(model, nblk, vmin, dv, 1e-15, 6, seed, cells,
+                                   threads=threads)
+    dt = 0.5 * dx[0] / 1485e3
+    name = "maxwellian-sparse-%dx%dx%d-v100" % tuple(n)
+    w = Workload(name, tuple(n), dx, nblk, vmin, dv, dt, steps, 1e-15, 6, storage, (0, 1, 2),
+                 offsets, ids, f, seed)
+    w.fields = {"n": dens, "T": temp, "V": vel}
+    return w
+
+
+def subbox_cells(n, lo, size, halo):
+    """Local-cell indices (x-fastest, periodic wrap) of the box
+    [lo - halo, lo + size + halo) of an n-box, in x-fastest order of the
+    padded sub-box."""
+    rng = [np.arange(lo[d] - halo, lo[d] + size[d] + halo) % n[d] for d in range(3)]
+    z, y, x = np.meshgrid(rng[2], rng[1], rng[0], indexing="ij")
+    return (x + n[0] * (y + n[1] * z)).reshape(-1)
+
+
+def take_cells(offsets, ids, f, cells):
+    """Gather the CSR rows `cells` of a state into a new CSR state."""
+    cells = np.asarray(cells, dtype=np.int64)
+    counts = offsets[cells + 1] - offsets[cells]
+    no = np.zeros(cells.size + 1, dtype=np.int64)
+    np.cumsum(counts, out=no[1:])
+    if no[-1] == 0:
+        return no, np.zeros(0, np.int32), np.zeros(0)
+    starts = np.repeat(offsets[cells] - no[:-1], counts)
+    blk = np.arange(no[-1]) + starts
+    ni = ids[blk]
+    nf = f.reshape(-1, 64)[blk].reshape(-1)
+    return no, ni, nf
