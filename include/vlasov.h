@@ -1,0 +1,182 @@
+/*
+ * vlasov.h — C ABI of libvlasov.so: the Vlasov translation solver on one
+ * MI355X (gfx950), for one partition padded with a coalesced ghost domain.
+ *
+ * Method (Battarbee et al., "Coalescing MPI communication in 6D Vlasov
+ * simulations: solving ghost domains in Vlasiator"):
+ *  - translation = the v . grad_x f term of the Vlasov equation (Section 2,
+ *    eq. 1), split into three Cartesian shears done in a fixed order
+ *    (Section 2.1);
+ *  - each shear is a conservative semi-Lagrangian piecewise-parabolic remap
+ *    along pencils of spatial cells with a 2-cell stencil; |v dt / dx| <= 1
+ *    so that only face neighbours exchange mass (Section 2.1); PPM variant:
+ *    Colella & Woodward (1984) with fourth-order faces and the monotonicity
+ *    limiter;
+ *  - velocity space is stored sparsely in 4x4x4 blocks that are added and
+ *    removed as the distribution evolves (Section 2);
+ *  - Ghost Translation (Section 3, 3.1, Fig. 3): one ghost update per step
+ *    of a halo 3 cells deep (2-cell stencil + 1 face neighbour, the "full"
+ *    GT3 set of Section 3.2); the first two shears are also computed on the
+ *    ghost cells that later shears read.  The classical scheme (Section 2.1,
+ *    Fig. 1) refreshes the current direction's ghost faces before each shear.
+ *
+ * Conventions
+ *  - Spatial cells: local box n[0] x n[1] x n[2], periodic, x fastest.  The
+ *    library allocates the padded box (n + 6 per axis) inside the workspace.
+ *  - Velocity mesh: nblk[d] blocks of 4 cells per axis.  Block id
+ *    b = bx + nblk[0] * (by + nblk[1] * bz); lane l = ix + 4 iy + 16 iz within
+ *    a block; cell-centre velocity v_d = vmin[d] + (4 b_d + i_d + 1/2) dv[d].
+ *  - f: phase-space density [s^3 m^-6] as cell volume averages.
+ *  - Every call is ordered on the HIP stream given at init.  Only calls that
+ *    say so synchronise the stream.
+ *  - Ownership: the caller allocates the device workspace
+ *    (vl_workspace_bytes) and keeps it alive until vl_destroy; the library
+ *    never allocates device memory.  Host input arrays are read during the
+ *    call only.  Device output arrays are written in stream order.
+ *  - Status: 0 = VL_OK, negative = error (vl_status_string).  On VL_ERR_ARG
+ *    and VL_ERR_CFL nothing has been enqueued.  Device-side overflow of a
+ *    capacity is recorded on the device and reported as VL_ERR_CAPACITY by
+ *    the next call that synchronises; the partition is then invalid and must
+ *    be re-initialised with larger capacities.
+ *  - A handle is not thread-safe; separate handles on separate streams are
+ *    independent.
+ */
+#ifndef VLASOV_H
+#define VLASOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { VL_F64 = 0, VL_F32 = 1, VL_BF16 = 2 };          /* storage of f */
+enum { VL_COALESCED = 0, VL_PER_SWEEP = 1 };            /* ghost scheme */
+enum {
+    VL_OK = 0,
+    VL_ERR_ARG = -1,          /* bad descriptor, pointer or size */
+    VL_ERR_CFL = -2,          /* some |v dt / dx| > 1 (Section 2.1) */
+    VL_ERR_CAPACITY = -3,     /* block, list or work-list capacity exceeded */
+    VL_ERR_STALE_GHOSTS = -4, /* coalesced step without a ghost update */
+    VL_ERR_HIP = -5,          /* a HIP runtime call failed */
+    VL_ERR_STATE = -6         /* partition invalid after an earlier error */
+};
+
+/* Partition descriptor (all fields are read by vl_workspace_bytes and
+ * vl_init_partition; none may change afterwards). */
+typedef struct vl_desc {
+    int32_t n[3];         /* local cells per axis, >= 1 each; n[d] + 6 <= 256 */
+    int32_t nblk[3];      /* velocity blocks per axis; product <= 131072 */
+    int32_t order[3];     /* shear order, a permutation of {0,1,2}; x->y->z = {0,1,2};
+                             the paper's Z->X->Y = {2,0,1} */
+    int32_t storage;      /* VL_F64, VL_F32 or VL_BF16 */
+    int32_t stencil;      /* PPM stencil half-width; must be 2 (Section 2.1) */
+    int32_t gt_level;     /* ghost-translation level; must be 3 (exact GT3, Section 3.2) */
+    int32_t vbuffer;      /* velocity-space buffer kept around content blocks:
+                             0, 6 (face neighbours) or 26 (all neighbours) */
+    int32_t reserved0;    /* must be 0 */
+    double dx[3];         /* spatial cell size [m], > 0 */
+    double vmin[3];       /* lower edge of the velocity mesh [m/s] */
+    double dv[3];         /* velocity cell size [m/s], > 0 */
+    double sparse_min;    /* content threshold [s^3 m^-6]: a block is kept if one of
+                             its values is >= sparse_min; <= 0 disables pruning */
+    int64_t block_capacity;       /* block slots for local cells (>= blocks at init) */
+    int64_t ghost_block_capacity; /* block slots for ghost cells */
+} vl_desc;
+
+/* Optional per-step report (vl_translate_step).  Masses are
+ * dx dy dz dvx dvy dvz * sum f over the local cells, in FP64. */
+typedef struct vl_step_stats {
+    double mass_before;   /* local mass before the step */
+    double mass_after;    /* local mass held in f after the step */
+    double pruned_mass;   /* mass of the blocks removed by pruning */
+    double ledger_mass;   /* FP32/BF16 storage: FP64 rounding residual kept outside
+                             f (0 for FP64) */
+    int64_t local_blocks; /* blocks held by local cells after the step */
+    int64_t updated_ps[3];/* phase-space cells written by each shear (sweep order) */
+    int64_t read_ps[3];   /* phase-space cells read by each shear */
+    int64_t items[3];     /* (pencil, block) work items of each shear */
+} vl_step_stats;
+
+typedef struct vl_partition vl_partition;
+
+/* Device workspace the partition needs, in bytes; 0 if the descriptor is
+ * invalid.  Covers the block pool (block_capacity + ghost_block_capacity
+ * blocks of 64 values), block lists, work lists and counters. */
+size_t vl_workspace_bytes(const vl_desc *d);
+
+/* Create a partition and load its local cells (Section 2: f on a sparse
+ * velocity mesh).  Host inputs, local cells only, x fastest:
+ *   cell_offsets[n0*n1*n2 + 1]  CSR row pointers in blocks (cell_offsets[0] = 0)
+ *   block_ids[cell_offsets[end]] ascending ids per cell, 0 <= id < prod(nblk)
+ *   f[64 * cell_offsets[end]]    values, lane order within each block
+ * dev_workspace: >= vl_workspace_bytes(d) bytes of device memory, 256-byte
+ * aligned.  hip_stream: a hipStream_t (NULL = default stream).  Values are
+ * converted to the storage type (round to nearest even).  The ghost domain
+ * is invalid until vl_fill_ghosts.  Synchronises the stream.
+ * Errors: VL_ERR_ARG (descriptor, alignment, size, unsorted or out-of-range
+ * ids), VL_ERR_CAPACITY (more blocks than block_capacity), VL_ERR_HIP. */
+int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes,
+                      void *hip_stream, const int64_t *cell_offsets,
+                      const int32_t *block_ids, const double *f, vl_partition **out);
+
+/* Coalesced ghost update (Section 3, Fig. 3a): every cell of the padded box
+ * outside the local box receives the block list and values of its periodic
+ * image.  Once per step, before a VL_COALESCED step.  Asynchronous. */
+int vl_fill_ghosts(vl_partition *p);
+
+/* One translation step: three shears in desc.order (Section 2.1), each a PPM
+ * remap of every velocity cell along its spatial pencils with Courant number
+ * v dt / dx[d], followed by block pruning of the local cells.
+ *   mode VL_COALESCED: Ghost Translation; needs vl_fill_ghosts since the
+ *        last step (else VL_ERR_STALE_GHOSTS).
+ *   mode VL_PER_SWEEP: classical per-direction ghost refresh (Fig. 1).
+ * Both modes give the same local result bit for bit.  The ghost domain is
+ * stale afterwards.  dt > 0 [s].  stats: optional host output; if non-NULL
+ * the call synchronises and also reports device-side errors.
+ * Errors: VL_ERR_ARG, VL_ERR_CFL (checked on the host before launch),
+ * VL_ERR_STALE_GHOSTS, VL_ERR_CAPACITY (with stats), VL_ERR_STATE, VL_ERR_HIP. */
+int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *stats);
+
+/* Velocity moments of the local cells, FP64 (paper silent; textbook
+ * definitions): n = dv^3 sum f; V = dv^3 sum f v / n;
+ * P_ab = m_p dv^3 sum f (v_a - V_a)(v_b - V_b), m_p = 1.67262192e-27 kg.
+ * Device outputs, local cells x fastest: dev_n[ncell], dev_V3[3*ncell],
+ * dev_P6[6*ncell] in the order xx, yy, zz, xy, xz, yz (any may be NULL).
+ * host_total_mass: optional; sum n dx dy dz, synchronises if non-NULL. */
+int vl_moments(vl_partition *p, double *dev_n, double *dev_V3, double *dev_P6,
+               double *host_total_mass);
+
+/* Number of blocks held by the local cells.  Synchronises. */
+int vl_local_block_count(vl_partition *p, int64_t *out);
+
+/* Copy the local cells to host memory as CSR (ids ascending per cell, values
+ * converted to FP64): cell_offsets[ncell+1], block_ids[cap_blocks],
+ * f[64*cap_blocks].  VL_ERR_ARG if cap_blocks is too small.  Synchronises. */
+int vl_export_state(vl_partition *p, int64_t *cell_offsets, int32_t *block_ids, double *f,
+                    int64_t cap_blocks);
+
+/* As vl_export_state for the local cells listed in cells[0..ncells) (local
+ * x-fastest indices), in that order.  Synchronises. */
+int vl_export_cells(vl_partition *p, const int64_t *cells, int64_t ncells,
+                    int64_t *cell_offsets, int32_t *block_ids, double *f, int64_t cap_blocks);
+
+/* Test hook: replace the Courant numbers by table[d * stride + j] for
+ * velocity index j along axis d (|values| <= 1), e.g. to drive exact integer
+ * shifts; NULL restores v dt / dx.  Synchronises. */
+int vl_set_courant_override(vl_partition *p, const double *table, int32_t stride);
+
+/* Wait for the partition's stream and report device-side errors. */
+int vl_sync(vl_partition *p);
+
+/* Release the host-side handle (the workspace stays the caller's). */
+void vl_destroy(vl_partition *p);
+
+const char *vl_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VLASOV_H */

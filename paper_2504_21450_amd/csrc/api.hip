@@ -1,0 +1,649 @@
+// C ABI of libvlasov.so (declared in include/vlasov.h): argument checks,
+// workspace carving, initial upload, and the stream-ordered launch sequence of
+// the ghost update, the three shears and the end-of-step pruning.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "vl_internal.h"
+#include "vl_storage.h"
+
+using namespace vl;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int RED_DOUBLES = 1024;
+
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    size_t pool, ring, flags, lstart, lcount, lcapa, lid, lslot, rows, items, masks, ctl, cover, cellred,
+        red, cellcnt, total;
+    int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap;
+    int wlmax, cover_stride;
+};
+
+bool desc_ok(const vl_desc *d)
+{
+    if (!d) return false;
+    int64_t nb = 1;
+    for (int k = 0; k < 3; k++) {
+        if (d->n[k] < 1 || d->n[k] + 2 * H > MAXL) return false;
+        if (d->nblk[k] < 1) return false;
+        nb *= d->nblk[k];
+        if (!(d->dx[k] > 0.0) || !(d->dv[k] > 0.0) || !isfinite(d->vmin[k])) return false;
+        if (!isfinite(d->dx[k]) || !isfinite(d->dv[k])) return false;
+    }
+    if (nb > NB_MAX) return false;
+    int seen = 0;
+    for (int k = 0; k < 3; k++) {
+        if (d->order[k] < 0 || d->order[k] > 2) return false;
+        seen |= 1 << d->order[k];
+    }
+    if (seen != 7) return false;
+    if (d->storage != VL_F64 && d->storage != VL_F32 && d->storage != VL_BF16) return false;
+    if (d->stencil != 2 || d->gt_level != 3) return false;
+    if (d->vbuffer != 0 && d->vbuffer != 6 && d->vbuffer != 26) return false;
+    if (d->reserved0 != 0) return false;
+    if (!isfinite(d->sparse_min)) return false;
+    if (d->block_capacity < 1 || d->ghost_block_capacity < 1) return false;
+    // slots (and the scratch slot) must stay below the row flag bit
+    if (d->block_capacity + d->ghost_block_capacity + 1 >= (int64_t)NEWFLAG - 1) return false;
+    return true;
+}
+
+Layout make_layout(const vl_desc *d)
+{
+    Layout L{};
+    int64_t P[3];
+    for (int k = 0; k < 3; k++) P[k] = d->n[k] + 2 * H;
+    L.N = P[0] * P[1] * P[2];
+    L.nlocal = (int64_t)d->n[0] * d->n[1] * d->n[2];
+    L.nghost = L.N - L.nlocal;
+    const int64_t lcap = d->block_capacity, gcap = d->ghost_block_capacity;
+    L.LA = lcap + lcap / 4 + 32 * L.nlocal;
+    L.LG = gcap + gcap / 4 + 32 * L.nghost;
+    L.row_cap = lcap + gcap + 64;
+    const int64_t tot = lcap + gcap;
+    L.item_cap = tot <= (1 << 24) ? tot + 64 : std::max<int64_t>(1 << 24, tot / 2);
+    int maxP = std::max(P[0], std::max(P[1], P[2]));
+    L.wlmax = (maxP + 31) / 32;
+    int maxnv = 4 * std::max(d->nblk[0], std::max(d->nblk[1], d->nblk[2]));
+    L.cover_stride = maxnv;
+    const int bs = storage_bytes(d->storage);
+    size_t o = 0;
+    L.pool = o;    o = align_up(o + (size_t)(tot + 1) * BLK * bs);
+    L.ring = o;    o = align_up(o + (size_t)lcap * 4);
+    L.flags = o;   o = align_up(o + (size_t)lcap);
+    L.lstart = o;  o = align_up(o + (size_t)L.N * 8);
+    L.lcount = o;  o = align_up(o + (size_t)L.N * 4);
+    L.lcapa = o;   o = align_up(o + (size_t)L.N * 4);
+    const size_t nl = (size_t)(2 * L.LA + L.LG);
+    L.lid = o;     o = align_up(o + nl * 4);
+    L.lslot = o;   o = align_up(o + nl * 4);
+    L.rows = o;    o = align_up(o + (size_t)L.row_cap * 4);
+    L.items = o;   o = align_up(o + (size_t)L.item_cap * sizeof(Item));
+    L.masks = o;   o = align_up(o + (size_t)L.item_cap * L.wlmax * 4);
+    L.ctl = o;     o = align_up(o + sizeof(Ctl));
+    L.cover = o;   o = align_up(o + (size_t)3 * maxnv * 8);
+    L.cellred = o; o = align_up(o + (size_t)L.nlocal * 8);
+    L.red = o;     o = align_up(o + (size_t)RED_DOUBLES * 8);
+    L.cellcnt = o; o = align_up(o + (size_t)L.nlocal * 4);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct vl_partition {
+    vl_desc desc;
+    Layout lay;
+    Dev D;
+    hipStream_t stream;
+    char *ws;
+    int cur;            // local list region in use (0 or 1)
+    bool ghosts_valid;
+    bool bad;
+    bool has_cover;
+    std::vector<double> cover_host;
+};
+
+namespace {
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? VL_OK : VL_ERR_HIP; }
+
+#define VL_HIP(call)                                        \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) {                             \
+            fprintf(stderr, "libvlasov: %s failed: %s\n", #call, hipGetErrorString(e_)); \
+            return VL_ERR_HIP;                              \
+        }                                                   \
+    } while (0)
+
+double host_courant(const vl_partition *p, int d, int j, double dt)
+{
+    if (p->has_cover) return p->cover_host[(size_t)d * p->lay.cover_stride + j];
+    const vl_desc &s = p->desc;
+    volatile double v = s.vmin[d] + ((double)j + 0.5) * s.dv[d];
+    volatile double num = v * dt;
+    return num / s.dx[d];
+}
+
+int check_cfl(const vl_partition *p, double dt)
+{
+    for (int d = 0; d < 3; d++)
+        for (int j = 0; j < 4 * p->desc.nblk[d]; j++) {
+            double c = host_courant(p, d, j, dt);
+            if (!(fabs(c) <= 1.0)) return VL_ERR_CFL;
+        }
+    return VL_OK;
+}
+
+int device_status(vl_partition *p)
+{
+    unsigned long long err = 0;
+    VL_HIP(hipMemcpyAsync(&err, &p->D.ctl->err, sizeof(err), hipMemcpyDeviceToHost, p->stream));
+    VL_HIP(hipStreamSynchronize(p->stream));
+    if (err) {
+        p->bad = true;
+        return VL_ERR_CAPACITY;
+    }
+    return VL_OK;
+}
+
+void update_box(const vl_partition *p, int mode, int s, int lo[3], int hi[3])
+{
+    for (int e = 0; e < 3; e++) {
+        lo[e] = H;
+        hi[e] = H + p->desc.n[e];
+    }
+    if (mode == VL_COALESCED)
+        for (int t = s + 1; t < 3; t++) {
+            int e = p->desc.order[t];
+            lo[e] = 0;
+            hi[e] = p->D.P[e];
+        }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vl_workspace_bytes(const vl_desc *d)
+{
+    if (!desc_ok(d)) return 0;
+    return make_layout(d).total;
+}
+
+const char *vl_status_string(int s)
+{
+    switch (s) {
+    case VL_OK: return "ok";
+    case VL_ERR_ARG: return "invalid argument";
+    case VL_ERR_CFL: return "Courant number above 1 (|v dt / dx| > 1)";
+    case VL_ERR_CAPACITY: return "capacity exceeded (blocks, lists or work items); re-initialise larger";
+    case VL_ERR_STALE_GHOSTS: return "coalesced step without a ghost update since the last step";
+    case VL_ERR_HIP: return "HIP runtime error";
+    case VL_ERR_STATE: return "partition invalid after an earlier error";
+    default: return "unknown status";
+    }
+}
+
+int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                      const int64_t *cell_offsets, const int32_t *block_ids, const double *f,
+                      vl_partition **out)
+{
+    if (!out) return VL_ERR_ARG;
+    *out = nullptr;
+    if (!desc_ok(d) || !dev_workspace || !cell_offsets) return VL_ERR_ARG;
+    if (((uintptr_t)dev_workspace) % ALIGN) return VL_ERR_ARG;
+    Layout L = make_layout(d);
+    if (ws_bytes < L.total) return VL_ERR_ARG;
+    const int64_t NB = (int64_t)d->nblk[0] * d->nblk[1] * d->nblk[2];
+    if (cell_offsets[0] != 0) return VL_ERR_ARG;
+    for (int64_t q = 0; q < L.nlocal; q++)
+        if (cell_offsets[q + 1] < cell_offsets[q]) return VL_ERR_ARG;
+    const int64_t total = cell_offsets[L.nlocal];
+    if (total > 0 && (!block_ids || !f)) return VL_ERR_ARG;
+    for (int64_t q = 0; q < L.nlocal; q++)
+        for (int64_t k = cell_offsets[q]; k < cell_offsets[q + 1]; k++) {
+            if (block_ids[k] < 0 || block_ids[k] >= NB) return VL_ERR_ARG;
+            if (k > cell_offsets[q] && block_ids[k] <= block_ids[k - 1]) return VL_ERR_ARG;
+        }
+    if (total > d->block_capacity) return VL_ERR_CAPACITY;
+
+    vl_partition *p = new vl_partition();
+    p->desc = *d;
+    p->lay = L;
+    p->stream = (hipStream_t)hip_stream;
+    p->ws = (char *)dev_workspace;
+    p->cur = 0;
+    p->ghosts_valid = false;
+    p->bad = false;
+    p->has_cover = false;
+
+    Dev &D = p->D;
+    memset(&D, 0, sizeof(D));
+    for (int k = 0; k < 3; k++) {
+        D.n[k] = d->n[k];
+        D.P[k] = d->n[k] + 2 * H;
+        D.nblk[k] = d->nblk[k];
+        D.vmin[k] = d->vmin[k];
+        D.dv[k] = d->dv[k];
+        D.dx[k] = d->dx[k];
+    }
+    D.NB = (int)NB;
+    D.W = (int)((NB + 31) / 32);
+    D.storage = d->storage;
+    D.vbuffer = d->vbuffer;
+    D.N = L.N;
+    D.nlocal = L.nlocal;
+    D.s[0] = 1;
+    D.s[1] = D.P[0];
+    D.s[2] = (int64_t)D.P[0] * D.P[1];
+    D.sparse_min = d->sparse_min;
+    char *w = p->ws;
+    D.pool = w + L.pool;
+    D.lcap = d->block_capacity;
+    D.gcap = d->ghost_block_capacity;
+    D.trash = D.lcap + D.gcap;
+    D.ring = (int32_t *)(w + L.ring);
+    D.flags = (uint8_t *)(w + L.flags);
+    D.lstart = (int64_t *)(w + L.lstart);
+    D.lcount = (int32_t *)(w + L.lcount);
+    D.lcapa = (int32_t *)(w + L.lcapa);
+    D.lid = (int32_t *)(w + L.lid);
+    D.lslot = (int32_t *)(w + L.lslot);
+    D.reg_off[0] = 0;
+    D.reg_cap[0] = L.LA;
+    D.reg_off[1] = L.LA;
+    D.reg_cap[1] = L.LA;
+    D.reg_off[2] = 2 * L.LA;
+    D.reg_cap[2] = L.LG;
+    D.rows = (int32_t *)(w + L.rows);
+    D.row_cap = L.row_cap;
+    D.items = (Item *)(w + L.items);
+    D.masks = (uint32_t *)(w + L.masks);
+    D.item_cap = L.item_cap;
+    D.wlmax = L.wlmax;
+    D.ctl = (Ctl *)(w + L.ctl);
+    D.cover = nullptr;
+    D.cover_stride = L.cover_stride;
+    D.cell_red = (double *)(w + L.cellred);
+    D.red = (double *)(w + L.red);
+    D.cell_cnt = (int32_t *)(w + L.cellcnt);
+
+    // host-side construction of cell metadata and local lists (region 0)
+    std::vector<int64_t> lstart(L.N, D.reg_off[2]);
+    std::vector<int32_t> lcount(L.N, 0), lcapa(L.N, 0);
+    std::vector<int32_t> lid, lslot;
+    lid.reserve(total + total / 4 + 32 * L.nlocal);
+    lslot.reserve(lid.capacity());
+    int64_t run = 0;
+    for (int64_t q = 0; q < L.nlocal; q++) {
+        const int x = (int)(q % d->n[0]), y = (int)((q / d->n[0]) % d->n[1]),
+                  z = (int)(q / ((int64_t)d->n[0] * d->n[1]));
+        const int64_t c = cell_index(D, x + H, y + H, z + H);
+        const int64_t b0 = cell_offsets[q], b1 = cell_offsets[q + 1];
+        const int cnt = (int)(b1 - b0);
+        const int cap = cnt + cnt / 4 + 32;
+        lstart[c] = run;
+        lcount[c] = cnt;
+        lcapa[c] = cap;
+        for (int64_t k = b0; k < b1; k++) {
+            lid.push_back(block_ids[k]);
+            lslot.push_back((int32_t)k);
+        }
+        for (int k = cnt; k < cap; k++) {
+            lid.push_back(0);
+            lslot.push_back(0);
+        }
+        run += cap;
+    }
+    int rc = VL_OK;
+    do {
+        Ctl ctl;
+        memset(&ctl, 0, sizeof(ctl));
+        ctl.ring_head = 0;
+        ctl.ring_tail = (unsigned long long)(D.lcap - total);
+        ctl.ring_limit = ctl.ring_tail;
+        if (hipMemcpy(D.ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        if (hipMemcpy(D.lstart, lstart.data(), L.N * 8, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        if (hipMemcpy(D.lcount, lcount.data(), L.N * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        if (hipMemcpy(D.lcapa, lcapa.data(), L.N * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        if (!lid.empty()) {
+            if (hipMemcpy(D.lid, lid.data(), lid.size() * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
+            if (hipMemcpy(D.lslot, lslot.data(), lslot.size() * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        }
+        if (hipMemset(D.flags, 0, (size_t)D.lcap) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        // payload, converted to the storage type in chunks
+        const int bs = storage_bytes(d->storage);
+        const int64_t nval = total * BLK;
+        if (d->storage == VL_F64) {
+            if (nval > 0 && hipMemcpy(D.pool, f, (size_t)nval * 8, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        } else {
+            const int64_t chunk = 1 << 24;
+            std::vector<unsigned char> buf((size_t)std::min<int64_t>(chunk, std::max<int64_t>(nval, 1)) * bs);
+            for (int64_t o = 0; o < nval && rc == VL_OK; o += chunk) {
+                const int64_t m = std::min(chunk, nval - o);
+                if (d->storage == VL_F32) {
+                    float *bf = (float *)buf.data();
+                    for (int64_t i = 0; i < m; i++) bf[i] = (float)f[o + i];
+                } else {
+                    uint16_t *bh = (uint16_t *)buf.data();
+                    for (int64_t i = 0; i < m; i++) {
+                        // FP64 -> FP32 rounded to odd -> BF16 nearest even
+                        const double v = f[o + i];
+                        float t = (float)v;
+                        if ((double)t != v) {
+                            // round toward zero, then set the sticky bit
+                            if (fabs((double)t) > fabs(v)) t = nextafterf(t, 0.0f);
+                            uint32_t u;
+                            memcpy(&u, &t, 4);
+                            u |= 1u;
+                            memcpy(&t, &u, 4);
+                        }
+                        bh[i] = f32_to_bf16_rne(t);
+                    }
+                }
+                if (hipMemcpy((char *)D.pool + (size_t)o * bs, buf.data(), (size_t)m * bs, hipMemcpyHostToDevice) !=
+                    hipSuccess)
+                    rc = VL_ERR_HIP;
+            }
+            if (rc) break;
+        }
+        launch_iota_ring(D, total, D.lcap - total, p->stream);
+        if (hipGetLastError() != hipSuccess) { rc = VL_ERR_HIP; break; }
+        if (hipStreamSynchronize(p->stream) != hipSuccess) { rc = VL_ERR_HIP; break; }
+    } while (0);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return VL_OK;
+}
+
+int vl_fill_ghosts(vl_partition *p)
+{
+    if (!p) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    const Dev &D = p->D;
+    int lo[3] = {0, 0, 0}, hi[3] = {D.P[0], D.P[1], D.P[2]};
+    launch_book(D, BOOK_GHOST_RESET, p->stream);
+    launch_fill(D, lo, hi, p->stream);
+    VL_HIP(hipGetLastError());
+    p->ghosts_valid = true;
+    return VL_OK;
+}
+
+int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *stats)
+{
+    if (!p) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    if (mode != VL_COALESCED && mode != VL_PER_SWEEP) return VL_ERR_ARG;
+    if (!(dt > 0.0) || !isfinite(dt)) return VL_ERR_ARG;
+    if (check_cfl(p, dt)) return VL_ERR_CFL;
+    if (mode == VL_COALESCED && !p->ghosts_valid) return VL_ERR_STALE_GHOSTS;
+    const Dev &D = p->D;
+    hipStream_t st = p->stream;
+    if (stats) {
+        launch_cell_mass(D, st);
+        launch_reduce(D, D.cell_red, D.nlocal, D.red + 0, st);
+        VL_HIP(hipMemsetAsync(D.red + 3, 0, sizeof(double), st));  // ledger of this step
+    }
+    launch_book(D, BOOK_STEP_RESET, st);
+    for (int s = 0; s < 3; s++) {
+        const int d = p->desc.order[s];
+        int lo[3], hi[3];
+        update_box(p, mode, s, lo, hi);
+        if (mode == VL_PER_SWEEP) {
+            int flo[3], fhi[3];
+            for (int e = 0; e < 3; e++) {
+                flo[e] = H;
+                fhi[e] = H + D.n[e];
+            }
+            flo[d] = 0;
+            fhi[d] = D.P[d];
+            launch_book(D, BOOK_GHOST_RESET, st);
+            launch_fill(D, flo, fhi, st);
+        }
+        launch_book(D, BOOK_SWEEP_RESET, st);
+        launch_plan(D, d, s, lo, hi, dt, st);
+        launch_sweep(D, d, s, lo, hi, dt, s == 2, stats ? D.red + 3 : D.red + 4, st);
+    }
+    const int nxt = 1 - p->cur;
+    launch_book(D, nxt == 0 ? BOOK_PRUNE_RESET_A : BOOK_PRUNE_RESET_B, st);
+    launch_prune(D, nxt, st);
+    VL_HIP(hipGetLastError());
+    p->cur = nxt;
+    p->ghosts_valid = false;
+    if (stats) {
+        launch_reduce(D, D.cell_red, D.nlocal, D.red + 2, st);  // pruned mass
+        launch_cell_mass(D, st);
+        launch_reduce(D, D.cell_red, D.nlocal, D.red + 1, st);
+        launch_cell_counts(D, st);
+        VL_HIP(hipGetLastError());
+        double red[4];
+        Ctl ctl;
+        std::vector<int32_t> cc((size_t)D.nlocal);
+        VL_HIP(hipMemcpyAsync(red, D.red, sizeof(red), hipMemcpyDeviceToHost, st));
+        VL_HIP(hipMemcpyAsync(&ctl, D.ctl, sizeof(ctl), hipMemcpyDeviceToHost, st));
+        VL_HIP(hipMemcpyAsync(cc.data(), D.cell_cnt, cc.size() * 4, hipMemcpyDeviceToHost, st));
+        VL_HIP(hipStreamSynchronize(st));
+        const double vol = D.dx[0] * D.dx[1] * D.dx[2] * D.dv[0] * D.dv[1] * D.dv[2];
+        memset(stats, 0, sizeof(*stats));
+        stats->mass_before = red[0] * vol;
+        stats->mass_after = red[1] * vol;
+        stats->pruned_mass = red[2];
+        stats->ledger_mass = red[3] * vol;
+        int64_t nb = 0;
+        for (int32_t v : cc) nb += v;
+        stats->local_blocks = nb;
+        for (int s = 0; s < 3; s++) {
+            stats->updated_ps[s] = (int64_t)ctl.upd_ps[s];
+            stats->read_ps[s] = (int64_t)ctl.read_ps[s];
+            stats->items[s] = (int64_t)ctl.items[s];
+        }
+        if (ctl.err) {
+            p->bad = true;
+            return VL_ERR_CAPACITY;
+        }
+    }
+    return VL_OK;
+}
+
+int vl_moments(vl_partition *p, double *dev_n, double *dev_V3, double *dev_P6, double *host_total_mass)
+{
+    if (!p) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    const Dev &D = p->D;
+    launch_moments(D, dev_n, dev_V3, dev_P6, p->stream);
+    VL_HIP(hipGetLastError());
+    if (host_total_mass) {
+        launch_reduce(D, D.cell_red, D.nlocal, D.red + 5, p->stream);
+        VL_HIP(hipMemcpyAsync(host_total_mass, D.red + 5, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        return device_status(p);
+    }
+    return VL_OK;
+}
+
+int vl_sync(vl_partition *p)
+{
+    if (!p) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    return device_status(p);
+}
+
+int vl_local_block_count(vl_partition *p, int64_t *out)
+{
+    if (!p || !out) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    const Dev &D = p->D;
+    launch_cell_counts(D, p->stream);
+    std::vector<int32_t> cc((size_t)D.nlocal);
+    VL_HIP(hipMemcpyAsync(cc.data(), D.cell_cnt, cc.size() * 4, hipMemcpyDeviceToHost, p->stream));
+    int rc = device_status(p);
+    if (rc) return rc;
+    int64_t nb = 0;
+    for (int32_t v : cc) nb += v;
+    *out = nb;
+    return VL_OK;
+}
+
+int vl_export_cells(vl_partition *p, const int64_t *cells, int64_t ncells, int64_t *cell_offsets,
+                    int32_t *block_ids, double *f, int64_t cap_blocks)
+{
+    if (!p || !cells || ncells < 0 || !cell_offsets) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    const Dev &D = p->D;
+    for (int64_t i = 0; i < ncells; i++)
+        if (cells[i] < 0 || cells[i] >= D.nlocal) return VL_ERR_ARG;
+    int rc = device_status(p);
+    if (rc) return rc;
+    // cell metadata and the current local list region
+    std::vector<int64_t> ls(ncells);
+    std::vector<int32_t> lc(ncells);
+    for (int64_t i = 0; i < ncells; i++) {
+        const int64_t q = cells[i];
+        const int x = (int)(q % D.n[0]), y = (int)((q / D.n[0]) % D.n[1]), z = (int)(q / ((int64_t)D.n[0] * D.n[1]));
+        const int64_t c = cell_index(D, x + H, y + H, z + H);
+        VL_HIP(hipMemcpy(&ls[i], D.lstart + c, 8, hipMemcpyDeviceToHost));
+        VL_HIP(hipMemcpy(&lc[i], D.lcount + c, 4, hipMemcpyDeviceToHost));
+    }
+    int64_t total = 0;
+    cell_offsets[0] = 0;
+    for (int64_t i = 0; i < ncells; i++) {
+        total += lc[i];
+        cell_offsets[i + 1] = total;
+    }
+    if (total > cap_blocks) return VL_ERR_ARG;
+    if (total > 0 && (!block_ids || !f)) return VL_ERR_ARG;
+    std::vector<int32_t> slots((size_t)total);
+    std::vector<std::pair<int32_t, int32_t>> ent;
+    for (int64_t i = 0; i < ncells; i++) {
+        ent.resize(lc[i]);
+        std::vector<int32_t> a(lc[i]), b(lc[i]);
+        if (lc[i] > 0) {
+            VL_HIP(hipMemcpy(a.data(), D.lid + ls[i], (size_t)lc[i] * 4, hipMemcpyDeviceToHost));
+            VL_HIP(hipMemcpy(b.data(), D.lslot + ls[i], (size_t)lc[i] * 4, hipMemcpyDeviceToHost));
+        }
+        for (int k = 0; k < lc[i]; k++) ent[k] = {a[k], b[k]};
+        std::sort(ent.begin(), ent.end());
+        for (int k = 0; k < lc[i]; k++) {
+            block_ids[cell_offsets[i] + k] = ent[k].first;
+            slots[cell_offsets[i] + k] = ent[k].second;
+        }
+    }
+    // gather payloads through dead work-list buffers: slot list in the item
+    // area, FP64 values in the row area
+    const int64_t chunk = std::min<int64_t>((int64_t)(p->lay.row_cap * 4) / (BLK * 8),
+                                            (int64_t)(p->lay.item_cap * sizeof(Item)) / 4);
+    if (chunk < 1) return VL_ERR_STATE;
+    int32_t *dslots = (int32_t *)D.items;
+    double *dvals = (double *)D.rows;
+    for (int64_t o = 0; o < total; o += chunk) {
+        const int64_t m = std::min(chunk, total - o);
+        VL_HIP(hipMemcpyAsync(dslots, slots.data() + o, (size_t)m * 4, hipMemcpyHostToDevice, p->stream));
+        launch_gather(D, dslots, m, dvals, p->stream);
+        VL_HIP(hipGetLastError());
+        VL_HIP(hipMemcpyAsync(f + o * BLK, dvals, (size_t)m * BLK * 8, hipMemcpyDeviceToHost, p->stream));
+        VL_HIP(hipStreamSynchronize(p->stream));
+    }
+    return VL_OK;
+}
+
+int vl_export_state(vl_partition *p, int64_t *cell_offsets, int32_t *block_ids, double *f, int64_t cap_blocks)
+{
+    if (!p || !cell_offsets) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    const Dev &D = p->D;
+    int rc = device_status(p);
+    if (rc) return rc;
+    // bulk metadata copy, then per-cell assembly on the host
+    std::vector<int64_t> lstart((size_t)D.N);
+    std::vector<int32_t> lcount((size_t)D.N);
+    VL_HIP(hipMemcpy(lstart.data(), D.lstart, (size_t)D.N * 8, hipMemcpyDeviceToHost));
+    VL_HIP(hipMemcpy(lcount.data(), D.lcount, (size_t)D.N * 4, hipMemcpyDeviceToHost));
+    const int64_t roff = D.reg_off[p->cur], rcap = D.reg_cap[p->cur];
+    std::vector<int32_t> lid((size_t)rcap), lslot((size_t)rcap);
+    VL_HIP(hipMemcpy(lid.data(), D.lid + roff, (size_t)rcap * 4, hipMemcpyDeviceToHost));
+    VL_HIP(hipMemcpy(lslot.data(), D.lslot + roff, (size_t)rcap * 4, hipMemcpyDeviceToHost));
+    int64_t total = 0;
+    cell_offsets[0] = 0;
+    for (int64_t q = 0; q < D.nlocal; q++) {
+        const int x = (int)(q % D.n[0]), y = (int)((q / D.n[0]) % D.n[1]), z = (int)(q / ((int64_t)D.n[0] * D.n[1]));
+        total += lcount[cell_index(D, x + H, y + H, z + H)];
+        cell_offsets[q + 1] = total;
+    }
+    if (total > cap_blocks) return VL_ERR_ARG;
+    if (total > 0 && (!block_ids || !f)) return VL_ERR_ARG;
+    std::vector<int32_t> slots((size_t)total);
+    std::vector<std::pair<int32_t, int32_t>> ent;
+    for (int64_t q = 0; q < D.nlocal; q++) {
+        const int x = (int)(q % D.n[0]), y = (int)((q / D.n[0]) % D.n[1]), z = (int)(q / ((int64_t)D.n[0] * D.n[1]));
+        const int64_t c = cell_index(D, x + H, y + H, z + H);
+        const int64_t s0 = lstart[c] - roff;
+        const int cnt = lcount[c];
+        if (cnt > 0 && (s0 < 0 || s0 + cnt > rcap)) return VL_ERR_STATE;
+        ent.resize(cnt);
+        for (int k = 0; k < cnt; k++) ent[k] = {lid[s0 + k], lslot[s0 + k]};
+        std::sort(ent.begin(), ent.end());
+        for (int k = 0; k < cnt; k++) {
+            block_ids[cell_offsets[q] + k] = ent[k].first;
+            slots[cell_offsets[q] + k] = ent[k].second;
+        }
+    }
+    const int64_t chunk = std::min<int64_t>((int64_t)(p->lay.row_cap * 4) / (BLK * 8),
+                                            (int64_t)(p->lay.item_cap * sizeof(Item)) / 4);
+    if (chunk < 1) return VL_ERR_STATE;
+    int32_t *dslots = (int32_t *)D.items;
+    double *dvals = (double *)D.rows;
+    for (int64_t o = 0; o < total; o += chunk) {
+        const int64_t m = std::min(chunk, total - o);
+        VL_HIP(hipMemcpyAsync(dslots, slots.data() + o, (size_t)m * 4, hipMemcpyHostToDevice, p->stream));
+        launch_gather(D, dslots, m, dvals, p->stream);
+        VL_HIP(hipGetLastError());
+        VL_HIP(hipMemcpyAsync(f + o * BLK, dvals, (size_t)m * BLK * 8, hipMemcpyDeviceToHost, p->stream));
+        VL_HIP(hipStreamSynchronize(p->stream));
+    }
+    return VL_OK;
+}
+
+int vl_set_courant_override(vl_partition *p, const double *table, int32_t stride)
+{
+    if (!p) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    if (!table) {
+        p->has_cover = false;
+        p->D.cover = nullptr;
+        return VL_OK;
+    }
+    const int cs = p->lay.cover_stride;
+    for (int d = 0; d < 3; d++)
+        if (stride < 4 * p->desc.nblk[d]) return VL_ERR_ARG;
+    std::vector<double> t((size_t)3 * cs, 0.0);
+    for (int d = 0; d < 3; d++)
+        for (int j = 0; j < 4 * p->desc.nblk[d]; j++) {
+            double v = table[(size_t)d * stride + j];
+            if (!(fabs(v) <= 1.0)) return VL_ERR_CFL;
+            t[(size_t)d * cs + j] = v;
+        }
+    double *dst = (double *)(p->ws + p->lay.cover);
+    VL_HIP(hipStreamSynchronize(p->stream));
+    VL_HIP(hipMemcpy(dst, t.data(), t.size() * 8, hipMemcpyHostToDevice));
+    p->cover_host = t;
+    p->has_cover = true;
+    p->D.cover = dst;
+    return VL_OK;
+}
+
+void vl_destroy(vl_partition *p) { delete p; }
+
+}  // extern "C"

@@ -1,0 +1,386 @@
+// Shear planner: one workgroup per pencil (a line of padded cells along the
+// shear axis d).  It
+//   1. builds the union of the block ids held by the pencil's cells (an LDS
+//      bitmap over the block-id space) and ranks it,
+//   2. records, per block of the union, which cells of the pencil hold it (a
+//      presence mask over the pencil),
+//   3. grows the block lists of the updated cells: a cell gains every block of
+//      its upwind face neighbour that moves into it (bit shifts of the
+//      presence masks), allocating slots for the new blocks,
+//   4. emits one work item per block held by an updated cell: its id, its
+//      presence mask and a compacted row of the slots of the cells holding it.
+// Each cell belongs to exactly one pencil of a shear, so the workgroup owns the
+// lists it grows.  Block ids of a chunk of the union are processed at a time
+// so the LDS footprint is bounded.
+#include "vl_internal.h"
+
+namespace vl {
+
+struct PlanParams {
+    int d, sidx;
+    int e1, e2;          // transverse axes
+    int lo1, n1, lo2, n2;  // pencil ranges (padded coordinates)
+    int L, WL;           // pencil length (padded extent along d), mask words
+    int ulo, uhi;        // updated cells along d
+    int R;               // chunk capacity (block ids per chunk)
+    double dt;
+};
+
+__device__ inline int popc(uint32_t v) { return __popc(v); }
+
+// exclusive scan of a[0..n) in place (LDS) by 256 threads; returns the total
+__device__ int block_scan_excl(int *a, int n, int *s_tmp)
+{
+    const int tid = threadIdx.x;
+    const int per = (n + 255) / 256;
+    const int b = min(tid * per, n), e = min(b + per, n);
+    int sum = 0;
+    for (int i = b; i < e; i++) sum += a[i];
+    s_tmp[tid] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 256 partial sums
+    for (int o = 1; o < 256; o <<= 1) {
+        int v = (tid >= o) ? s_tmp[tid - o] : 0;
+        __syncthreads();
+        s_tmp[tid] += v;
+        __syncthreads();
+    }
+    int run = s_tmp[tid] - sum;
+    const int total = s_tmp[255];
+    for (int i = b; i < e; i++) {
+        int v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+    return total;
+}
+
+__device__ inline long long block_sum_ll(long long v, long long *s_tmp)
+{
+    const int tid = threadIdx.x;
+    s_tmp[tid] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) s_tmp[tid] += s_tmp[tid + o];
+        __syncthreads();
+    }
+    long long r = s_tmp[0];
+    __syncthreads();
+    return r;
+}
+
+// index of the pencil cell holding flat entry q (s_pre: prefix of counts, L+1)
+__device__ inline int find_cell(const int *s_pre, int L, int q)
+{
+    int lo = 0, hi = L;  // s_pre[lo] <= q < s_pre[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_tmp[256];
+    __shared__ long long s_ll[256];
+    __shared__ unsigned long long s_base[4];  // item, row, new-slot bases, status
+    const int tid = threadIdx.x;
+    const int L = pp.L, WL = pp.WL, W = D.W, R = pp.R;
+
+    // dynamic LDS carve
+    unsigned char *q = smem;
+    int64_t *s_cs = (int64_t *)q; q += sizeof(int64_t) * MAXL;
+    int *s_cnt = (int *)q; q += sizeof(int) * MAXL;
+    int *s_cap = (int *)q; q += sizeof(int) * MAXL;
+    int *s_new = (int *)q; q += sizeof(int) * MAXL;
+    int *s_pre = (int *)q; q += sizeof(int) * (MAXL + 4);
+    uint32_t *s_bm = (uint32_t *)q; q += sizeof(uint32_t) * W;
+    int *s_rank = (int *)q; q += sizeof(int) * (W + 1);
+    uint32_t *s_pres = (uint32_t *)q; q += sizeof(uint32_t) * R * WL;
+    uint32_t *s_newb = (uint32_t *)q; q += sizeof(uint32_t) * R * WL;
+    int *s_id = (int *)q; q += sizeof(int) * R;
+    int *s_ai = (int *)q; q += sizeof(int) * (R + 1);  // item prefix
+    int *s_ro = (int *)q; q += sizeof(int) * (R + 1);  // row prefix
+    int *s_np = (int *)q; q += sizeof(int) * (R + 1);  // new-block prefix
+
+    const int p = blockIdx.x;
+    const int t1 = pp.lo1 + p % pp.n1;
+    const int t2 = pp.lo2 + p / pp.n1;
+    int co[3];
+    co[pp.e1] = t1;
+    co[pp.e2] = t2;
+    co[pp.d] = 0;
+    const int64_t base = cell_index(D, co[0], co[1], co[2]);
+    const int64_t sd = D.s[pp.d];
+    const bool local_pencil = t1 >= H && t1 < H + D.n[pp.e1] && t2 >= H && t2 < H + D.n[pp.e2];
+
+    // 0. cell metadata
+    for (int i = tid; i < L; i += 256) {
+        const int64_t c = base + sd * i;
+        s_cs[i] = D.lstart[c];
+        s_cnt[i] = D.lcount[c];
+        s_cap[i] = D.lcapa[c];
+        s_new[i] = 0;
+    }
+    for (int w = tid; w < W; w += 256) s_bm[w] = 0u;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int i = 0; i < L; i++) {
+            s_pre[i] = run;
+            run += s_cnt[i];
+        }
+        s_pre[L] = run;
+    }
+    __syncthreads();
+    const int T = s_pre[L];
+
+    // 1. union bitmap
+    for (int qf = tid; qf < T; qf += 256) {
+        const int i = find_cell(s_pre, L, qf);
+        const int32_t id = D.lid[s_cs[i] + (qf - s_pre[i])];
+        atomicOr(&s_bm[id >> 5], 1u << (id & 31));
+    }
+    __syncthreads();
+    // 2. ranks
+    for (int w = tid; w < W; w += 256) s_rank[w] = popc(s_bm[w]);
+    __syncthreads();
+    const int U = block_scan_excl(s_rank, W, s_tmp);
+
+    // update-range mask
+    uint32_t um[MAXWL];
+#pragma unroll
+    for (int w = 0; w < MAXWL; w++) {
+        uint32_t m = 0;
+        for (int b = 0; b < 32; b++) {
+            int i = 32 * w + b;
+            if (i >= pp.ulo && i < pp.uhi) m |= 1u << b;
+        }
+        um[w] = m;
+    }
+
+    long long st_upd = 0, st_read = 0, st_items = 0;
+
+    for (int r0 = 0; r0 < U; r0 += R) {
+        const int rn = min(R, U - r0);
+        for (int k = tid; k < rn * WL; k += 256) s_pres[k] = 0u;
+        __syncthreads();
+        // presence masks of this chunk
+        for (int qf = tid; qf < T; qf += 256) {
+            const int i = find_cell(s_pre, L, qf);
+            const int32_t id = D.lid[s_cs[i] + (qf - s_pre[i])];
+            const int w = id >> 5;
+            const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
+            if (k >= 0 && k < rn) {
+                atomicOr(&s_pres[k * WL + (i >> 5)], 1u << (i & 31));
+                s_id[k] = id;
+            }
+        }
+        __syncthreads();
+        // growth and per-block counts
+        for (int k = tid; k < rn; k += 256) {
+            uint32_t P[MAXWL], G[MAXWL];
+#pragma unroll
+            for (int w = 0; w < MAXWL; w++) P[w] = (w < WL) ? s_pres[k * WL + w] : 0u;
+            const int dirs = block_dirs(D, pp.d, s_id[k], pp.dt);
+#pragma unroll
+            for (int w = 0; w < MAXWL; w++) {
+                uint32_t g = 0;
+                if (dirs & 1) g |= (P[w] << 1) | (w > 0 ? (P[w - 1] >> 31) : 0u);
+                if (dirs & 2) g |= (P[w] >> 1) | (w + 1 < MAXWL ? (P[w + 1] << 31) : 0u);
+                G[w] = g & ~P[w] & um[w];
+            }
+            int rowlen = 0, nnew = 0, upd = 0, rd = 0;
+            bool active = false;
+#pragma unroll
+            for (int w = 0; w < MAXWL; w++) {
+                if (w < WL) {
+                    const uint32_t pn = P[w] | G[w];
+                    s_pres[k * WL + w] = pn;
+                    s_newb[k * WL + w] = G[w];
+                    active |= (pn & um[w]) != 0u;
+                    rowlen += popc(pn);
+                    nnew += popc(G[w]);
+                    upd += popc(pn & um[w]);
+                    rd += popc(P[w]);
+                }
+            }
+            s_ai[k] = active ? 1 : 0;
+            s_ro[k] = active ? rowlen : 0;
+            s_np[k] = active ? nnew : 0;
+            if (active) {
+                st_upd += upd;
+                st_read += rd;
+                st_items += 1;
+            }
+        }
+        __syncthreads();
+        const int nact = block_scan_excl(s_ai, rn, s_tmp);
+        const int nrow = block_scan_excl(s_ro, rn, s_tmp);
+        const int nnew = block_scan_excl(s_np, rn, s_tmp);
+        if (tid == 0) {
+            s_ai[rn] = nact;
+            s_ro[rn] = nrow;
+            s_np[rn] = nnew;
+            unsigned long long err = 0;
+            unsigned long long ib = atomicAdd(&D.ctl->n_items, (unsigned long long)nact);
+            unsigned long long rb = atomicAdd(&D.ctl->row_top, (unsigned long long)nrow);
+            unsigned long long nb = 0;
+            unsigned long long ok = 1;
+            if ((int64_t)(rb + nrow) > D.row_cap) {
+                err |= E_ROWS;
+                ok = 0;
+            }
+            if ((int64_t)(ib + nact) > D.item_cap) err |= E_ITEMS;
+            if (nnew > 0) {
+                if (local_pencil) {
+                    nb = atomicAdd(&D.ctl->ring_head, (unsigned long long)nnew);
+                    if (nb + nnew > D.ctl->ring_limit) {
+                        err |= E_RING;
+                        ok |= 2;  // allocation failed: new blocks go to the scratch slot
+                    }
+                } else {
+                    nb = atomicAdd(&D.ctl->ghost_top, (unsigned long long)nnew);
+                    if ((int64_t)(nb + nnew) > D.gcap) {
+                        err |= E_GHOST_SLOTS;
+                        ok |= 2;
+                    }
+                }
+            }
+            if (err) atomicOr(&D.ctl->err, err);
+            s_base[0] = ib;
+            s_base[1] = rb;
+            s_base[2] = nb;
+            s_base[3] = ok;
+        }
+        __syncthreads();
+        const unsigned long long ib = s_base[0], rb = s_base[1], nb = s_base[2];
+        const bool rows_ok = (s_base[3] & 1) != 0;
+        const bool alloc_failed = (s_base[3] & 2) != 0;
+
+        // items and new blocks
+        for (int k = tid; k < rn; k += 256) {
+            if (s_ai[k + 1] == s_ai[k]) continue;  // inactive
+            const int64_t it = (int64_t)ib + s_ai[k];
+            const int64_t rowoff = (int64_t)rb + s_ro[k];
+            if (it < D.item_cap) {
+                Item item;
+                item.id = s_id[k];
+                item.pencil = p;
+                item.rowoff = rows_ok ? rowoff : 0;
+                D.items[it] = item;
+                for (int w = 0; w < D.wlmax; w++)
+                    D.masks[it * D.wlmax + w] = (rows_ok && w < WL) ? s_pres[k * WL + w] : 0u;
+            }
+            int qn = s_np[k];
+            for (int w = 0; w < WL; w++) {
+                uint32_t nbits = s_newb[k * WL + w];
+                while (nbits) {
+                    const int bit = __ffs(nbits) - 1;
+                    nbits &= nbits - 1;
+                    const int i = 32 * w + bit;
+                    int64_t slot;
+                    if (alloc_failed) {
+                        slot = D.trash;
+                    } else if (local_pencil) {
+                        slot = D.ring[(int64_t)((nb + qn) % (unsigned long long)D.lcap)];
+                    } else {
+                        slot = D.lcap + (int64_t)nb + qn;
+                    }
+                    qn++;
+                    if (rows_ok) {
+                        int pos = 0;
+                        for (int w2 = 0; w2 < w; w2++) pos += popc(s_pres[k * WL + w2]);
+                        pos += popc(s_pres[k * WL + w] & ((1u << bit) - 1u));
+                        D.rows[rowoff + pos] = (int32_t)((uint32_t)slot | NEWFLAG);
+                    }
+                    if (!alloc_failed) {
+                        const int lp = atomicAdd(&s_new[i], 1);
+                        if (s_cnt[i] + lp < s_cap[i]) {
+                            const int64_t at = s_cs[i] + s_cnt[i] + lp;
+                            D.lid[at] = s_id[k];
+                            D.lslot[at] = (int32_t)slot;
+                        } else {
+                            atomicOr(&D.ctl->err, (unsigned long long)E_LIST);
+                        }
+                    }
+                }
+            }
+        }
+        // rows of the blocks already held
+        if (rows_ok) {
+            for (int qf = tid; qf < T; qf += 256) {
+                const int i = find_cell(s_pre, L, qf);
+                const int64_t at = s_cs[i] + (qf - s_pre[i]);
+                const int32_t id = D.lid[at];
+                const int w = id >> 5;
+                const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
+                if (k < 0 || k >= rn) continue;
+                if (s_ai[k + 1] == s_ai[k]) continue;
+                int pos = 0;
+                const int iw = i >> 5;
+                for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
+                pos += popc(s_pres[k * WL + iw] & ((1u << (i & 31)) - 1u));
+                D.rows[(int64_t)rb + s_ro[k] + pos] = D.lslot[at];
+            }
+        }
+        __syncthreads();
+    }
+
+    // commit list growth
+    for (int i = tid; i < L; i += 256) {
+        const int a = s_new[i];
+        if (a > 0) D.lcount[base + sd * i] = min(s_cnt[i] + a, s_cap[i]);
+    }
+    const long long u = block_sum_ll(st_upd, s_ll);
+    const long long r = block_sum_ll(st_read, s_ll);
+    const long long n = block_sum_ll(st_items, s_ll);
+    if (tid == 0 && n > 0) {
+        atomicAdd(&D.ctl->upd_ps[pp.sidx], (unsigned long long)(u * BLK));
+        atomicAdd(&D.ctl->read_ps[pp.sidx], (unsigned long long)(r * BLK));
+        atomicAdd(&D.ctl->items[pp.sidx], (unsigned long long)n);
+    }
+}
+
+size_t plan_lds_bytes(int W, int R, int WL)
+{
+    size_t b = sizeof(int64_t) * MAXL + sizeof(int) * MAXL * 3 + sizeof(int) * (MAXL + 4);
+    b += sizeof(uint32_t) * W + sizeof(int) * (W + 1);
+    b += (size_t)R * WL * 4 * 2 + (size_t)R * 4 + (size_t)(R + 1) * 4 * 3;
+    return b + 64;
+}
+
+void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt,
+                 hipStream_t st)
+{
+    PlanParams pp;
+    pp.d = d;
+    pp.sidx = sidx;
+    pp.e1 = (d == 0) ? 1 : 0;
+    pp.e2 = (d == 2) ? 1 : 2;
+    pp.lo1 = lo[pp.e1];
+    pp.n1 = hi[pp.e1] - lo[pp.e1];
+    pp.lo2 = lo[pp.e2];
+    pp.n2 = hi[pp.e2] - lo[pp.e2];
+    pp.L = D.P[d];
+    pp.WL = (pp.L + 31) / 32;
+    pp.ulo = lo[d];
+    pp.uhi = hi[d];
+    pp.dt = dt;
+    // chunk size: keep the workgroup's LDS at <= 56 KiB
+    const size_t budget = 56 * 1024;
+    size_t fixed = plan_lds_bytes(D.W, 0, pp.WL);
+    size_t per = (size_t)pp.WL * 8 + 16;
+    int R = (fixed < budget) ? (int)((budget - fixed) / per) : 64;
+    if (R < 64) R = 64;
+    pp.R = R;
+    size_t lds = plan_lds_bytes(D.W, R, pp.WL);
+    int64_t np = (int64_t)pp.n1 * pp.n2;
+    if (np <= 0) return;
+    hipLaunchKernelGGL(k_plan, dim3((unsigned)np), dim3(256), lds, st, D, pp);
+}
+
+}  // namespace vl

@@ -1,0 +1,207 @@
+// End-of-step block pruning of the local cells (sparse velocity space,
+// Section 2: blocks are added and removed where necessary).  One workgroup per
+// local cell:
+//   content = blocks with a value >= sparse_min (flag set by the last shear),
+//   keep    = content dilated by the velocity-space buffer (0, 6 or 26
+//             neighbours, clipped to the mesh); keep = all blocks if pruning is
+//             off,
+//   removed blocks: their mass goes to the pruned-mass ledger and their slots
+//             back to the free ring; created blocks get zeroed slots,
+//   the list is rewritten sorted by block id into the other local list
+//             region, with fresh slack for the next step's growth.
+#include "vl_internal.h"
+#include "vl_storage.h"
+
+namespace vl {
+
+__device__ inline int popc32(uint32_t v) { return __popc(v); }
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_tmp[256];
+    __shared__ double s_wmass[4];
+    __shared__ unsigned long long s_base[3];
+    __shared__ int s_cnt[3];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int W = D.W;
+    uint32_t *s_old = (uint32_t *)smem;
+    uint32_t *s_keep = s_old + W;
+    int *s_rank = (int *)(s_keep + W);
+
+    const int64_t q = blockIdx.x;
+    const int x = (int)(q % D.n[0]), y = (int)((q / D.n[0]) % D.n[1]), z = (int)(q / ((int64_t)D.n[0] * D.n[1]));
+    const int64_t c = cell_index(D, x + H, y + H, z + H);
+    const int cnt = D.lcount[c];
+    const int64_t cs = D.lstart[c];
+    const bool prune = D.sparse_min > 0.0;
+
+    for (int w = tid; w < W; w += 256) {
+        s_old[w] = 0u;
+        s_keep[w] = 0u;
+    }
+    if (tid < 3) s_cnt[tid] = 0;
+    __syncthreads();
+    for (int e = tid; e < cnt; e += 256) {
+        const int32_t id = D.lid[cs + e];
+        atomicOr(&s_old[id >> 5], 1u << (id & 31));
+    }
+    __syncthreads();
+    if (prune) {
+        const int nbx = D.nblk[0], nby = D.nblk[1], nbz = D.nblk[2];
+        for (int e = tid; e < cnt; e += 256) {
+            const int32_t slot = D.lslot[cs + e];
+            if ((int64_t)slot >= D.lcap || !D.flags[slot]) continue;
+            const int32_t id = D.lid[cs + e];
+            const int bx = id % nbx, by = (id / nbx) % nby, bz = id / (nbx * nby);
+            for (int oz = -1; oz <= 1; oz++)
+                for (int oy = -1; oy <= 1; oy++)
+                    for (int ox = -1; ox <= 1; ox++) {
+                        const int nz = (ox != 0) + (oy != 0) + (oz != 0);
+                        if (nz > 1 && D.vbuffer != 26) continue;
+                        if (nz == 1 && D.vbuffer == 0) continue;
+                        const int xx = bx + ox, yy = by + oy, zz = bz + oz;
+                        if (xx < 0 || yy < 0 || zz < 0 || xx >= nbx || yy >= nby || zz >= nbz) continue;
+                        const int32_t nid = xx + nbx * (yy + nby * zz);
+                        atomicOr(&s_keep[nid >> 5], 1u << (nid & 31));
+                    }
+        }
+    } else {
+        for (int w = tid; w < W; w += 256) s_keep[w] = s_old[w];
+    }
+    __syncthreads();
+    // ranks of the kept blocks and counts
+    int ncreate = 0;
+    for (int w = tid; w < W; w += 256) {
+        s_rank[w] = popc32(s_keep[w]);
+        ncreate += popc32(s_keep[w] & ~s_old[w]);
+    }
+    atomicAdd(&s_cnt[1], ncreate);
+    __syncthreads();
+    // exclusive scan of s_rank (W words) by 256 threads
+    {
+        const int per = (W + 255) / 256;
+        const int b = min(tid * per, W), e = min(b + per, W);
+        int sum = 0;
+        for (int i = b; i < e; i++) sum += s_rank[i];
+        s_tmp[tid] = sum;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            int v = (tid >= o) ? s_tmp[tid - o] : 0;
+            __syncthreads();
+            s_tmp[tid] += v;
+            __syncthreads();
+        }
+        int run = s_tmp[tid] - sum;
+        for (int i = b; i < e; i++) {
+            int v = s_rank[i];
+            s_rank[i] = run;
+            run += v;
+        }
+        if (tid == 255) s_cnt[0] = s_tmp[255];
+    }
+    __syncthreads();
+    const int nkeep = s_cnt[0];
+    const int ncr = s_cnt[1];
+    const int cap = nkeep + nkeep / 4 + 32;
+    if (tid == 0) {
+        unsigned long long err = 0;
+        unsigned long long lb = atomicAdd(&D.ctl->list_top[nxt], (unsigned long long)cap);
+        unsigned long long ok = 1;
+        if ((int64_t)(lb + cap) > D.reg_cap[nxt]) {
+            err |= E_LOCAL_LIST;
+            ok = 0;
+        }
+        unsigned long long rb = 0;
+        if (ok && ncr > 0) {
+            rb = atomicAdd(&D.ctl->ring_head, (unsigned long long)ncr);
+            if (rb + ncr > D.ctl->ring_limit) {
+                err |= E_RING;
+                ok |= 2;
+            }
+        }
+        if (err) atomicOr(&D.ctl->err, err);
+        s_base[0] = lb;
+        s_base[1] = rb;
+        s_base[2] = ok;
+        s_cnt[2] = 0;
+    }
+    __syncthreads();
+    if (!(s_base[2] & 1)) {
+        if (tid == 0) D.cell_red[q] = 0.0;
+        return;  // list region full: the cell keeps its old list (error flagged)
+    }
+    const int64_t ns = D.reg_off[nxt] + (int64_t)s_base[0];
+    const bool ring_failed = (s_base[2] & 2) != 0;
+
+    // old entries, one wavefront per entry: keep (move to the new list) or
+    // remove (sum its mass in FP64, return the slot to the ring)
+    double wmass = 0.0;
+    for (int e = wv; e < cnt; e += 4) {
+        const int32_t id = D.lid[cs + e];
+        const int32_t slot = D.lslot[cs + e];
+        const int w = id >> 5;
+        const uint32_t bit = 1u << (id & 31);
+        if (s_keep[w] & bit) {
+            if (lane == 0) {
+                const int pos = s_rank[w] + popc32(s_keep[w] & (bit - 1u));
+                D.lid[ns + pos] = id;
+                D.lslot[ns + pos] = slot;
+            }
+        } else {
+            double v = Storage<ST>::load(D.pool, (int64_t)slot * BLK + lane);
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            wmass += v;
+            if (lane == 0 && (int64_t)slot < D.lcap) {
+                const unsigned long long t = atomicAdd(&D.ctl->ring_tail, 1ull);
+                D.ring[(int64_t)(t % (unsigned long long)D.lcap)] = slot;
+            }
+        }
+    }
+    // created blocks, one wavefront per block: take a slot, zero it
+    for (int w = 0; w < W; w++) {
+        uint32_t cr = s_keep[w] & ~s_old[w];
+        while (cr) {
+            const int bit = __ffs(cr) - 1;
+            cr &= cr - 1;
+            // block (w, bit) is handled by wave (rank % 4)
+            const int32_t id = 32 * w + bit;
+            const int pos = s_rank[w] + popc32(s_keep[w] & ((1u << bit) - 1u));
+            const int k = pos;  // distinct per created block
+            if ((k & 3) != wv) continue;
+            int ci = 0;
+            if (lane == 0) ci = atomicAdd(&s_cnt[2], 1);
+            ci = __shfl(ci, 0);
+            int64_t slot = ring_failed ? D.trash
+                                       : (int64_t)D.ring[(int64_t)((s_base[1] + ci) % (unsigned long long)D.lcap)];
+            Storage<ST>::store(D.pool, slot * BLK + lane, 0.0);
+            if (lane == 0) {
+                D.lid[ns + pos] = id;
+                D.lslot[ns + pos] = (int32_t)slot;
+            }
+        }
+    }
+    if (lane == 0) s_wmass[wv] = wmass;
+    __syncthreads();
+    if (tid == 0) {
+        D.cell_red[q] = (((s_wmass[0] + s_wmass[1]) + s_wmass[2]) + s_wmass[3]) * vol;
+        D.lstart[c] = ns;
+        D.lcount[c] = nkeep;
+        D.lcapa[c] = cap;
+    }
+}
+
+void launch_prune(const Dev &D, int nxt, hipStream_t st)
+{
+    size_t lds = sizeof(uint32_t) * D.W * 2 + sizeof(int) * (D.W + 1) + 64;
+    const double vol = D.dx[0] * D.dx[1] * D.dx[2] * D.dv[0] * D.dv[1] * D.dv[2];
+    dim3 g((unsigned)D.nlocal), b(256);
+    switch (D.storage) {
+    case VL_F64: hipLaunchKernelGGL(k_prune<VL_F64>, g, b, lds, st, D, nxt, vol); break;
+    case VL_F32: hipLaunchKernelGGL(k_prune<VL_F32>, g, b, lds, st, D, nxt, vol); break;
+    default: hipLaunchKernelGGL(k_prune<VL_BF16>, g, b, lds, st, D, nxt, vol); break;
+    }
+}
+
+}  // namespace vl

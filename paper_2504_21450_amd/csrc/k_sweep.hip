@@ -1,0 +1,248 @@
+// PPM shear kernel.  Persistent: each wavefront repeatedly takes the next
+// (pencil, velocity block) work item from the list built by the planner and
+// marches along the pencil, one lane per velocity cell of the block (64 lanes
+// = 4x4x4 cells), with the reconstruction state in registers:
+//   slope of cell t-1      (Colella & Woodward 1984, eq. 1.7-1.8)
+//   face value t-3/2       (eq. 1.6, uniform grid)
+//   limited profile t-2    (eq. 1.10)
+//   flux through t-5/2     (eq. 1.12; upwind cell chosen by the sign of the
+//                           lane's Courant number)
+//   new average of t-3  =  old average + F(t-7/2) - F(t-5/2), written in place.
+// Each (cell, block) belongs to exactly one item of a shear, so the update is
+// in place without a second buffer.  Cells that do not hold the block read as
+// zero; blocks created by the planner's growth step read as zero too.
+//
+// Storage variants:
+//   VL_F64 : everything in FP64.
+//   VL_F32 / VL_BF16 : values are loaded into FP32; slopes, faces and the
+//            limiter run in FP32; the Courant number, flux integral and update
+//            in FP64.  The FP64 update is rounded to the storage type and the
+//            rounding residual is carried along the pencil into the next
+//            updated cell, so a pencil's mass changes only by its final
+//            residual, which is accumulated in an FP64 ledger.
+#include "vl_internal.h"
+#include "vl_storage.h"
+
+namespace vl {
+
+struct SweepParams {
+    int d, sidx, L, WL;
+    int e1, e2, lo1, n1, lo2;  // pencil geometry (to tell local pencils)
+    double dt;
+    double sparse_min;
+    double *ledger;            // FP64 accumulator of terminal residuals (mixed storage)
+};
+
+__device__ inline void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename F>
+struct Recon {
+    // slope of the middle cell of (am, a0, ap)
+    __device__ static F slope(F am, F a0, F ap)
+    {
+        const F dl = a0 - am, dr = ap - a0;
+        const F cen = (F)0.5 * (ap - am);
+        F m = fmin(fabs(cen), (F)2.0 * fabs(dl));
+        m = fmin(m, (F)2.0 * fabs(dr));
+        const F s = cen > (F)0 ? m : -m;
+        return (dl * dr > (F)0) ? s : (F)0;
+    }
+    // limited parabola of cell value a between faces l and r: returns edge
+    // (right face if pos else left face), dA = r - l and a6
+    __device__ static void limit(F a, F l, F r, bool pos, F &edge, F &dA, F &a6)
+    {
+        const bool flat = (r - a) * (a - l) <= (F)0;
+        const F dd = r - l;
+        const F mm = a - (F)0.5 * (l + r);
+        const F dm = dd * mm;
+        const F d26 = dd * dd * (F)(1.0 / 6.0);
+        const bool b1 = dm > d26;
+        const bool b2 = !b1 && (-d26 > dm);
+        F ll = b1 ? (F)3.0 * a - (F)2.0 * r : l;
+        F rr = b2 ? (F)3.0 * a - (F)2.0 * l : r;
+        ll = flat ? a : ll;
+        rr = flat ? a : rr;
+        dA = rr - ll;
+        a6 = (F)6.0 * (a - (F)0.5 * (ll + rr));
+        edge = pos ? rr : ll;
+    }
+};
+
+constexpr uint32_t ABSENT = 0xffffffffu;
+constexpr int PF = 8;  // cells prefetched ahead of the reconstruction front
+
+template <int ST, bool LAST>
+__global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
+{
+    using C = typename std::conditional<ST == VL_F64, double, float>::type;  // reconstruction type
+    __shared__ uint32_t s_slot[4][MAXL + PF];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int d = sp.d, L = sp.L, WL = sp.WL;
+    const int ld = (d == 0) ? (lane & 3) : (d == 1) ? ((lane >> 2) & 3) : (lane >> 4);
+    const int64_t nitems = min((int64_t)D.ctl->n_items, D.item_cap);
+    uint32_t *srow = s_slot[wv];
+    double ledger_acc = 0.0;
+
+    for (;;) {
+        unsigned long long itu = 0;
+        if (lane == 0) itu = atomicAdd(&D.ctl->work, 1ull);
+        const int64_t it = (int64_t)__shfl(itu, 0);
+        if (it >= nitems) break;
+        const Item item = D.items[it];
+        // per-cell slot table of this item in LDS: slot, slot|NEWFLAG or ABSENT
+        {
+            uint32_t m[MAXWL];
+            int pre[MAXWL + 1];
+            pre[0] = 0;
+#pragma unroll
+            for (int w = 0; w < MAXWL; w++) {
+                m[w] = (w < WL) ? D.masks[it * D.wlmax + w] : 0u;
+                pre[w + 1] = pre[w] + __popc(m[w]);
+            }
+            if (pre[MAXWL] == 0) continue;
+            const int half = lane >> 5, b = lane & 31;
+#pragma unroll
+            for (int w = 0; w < MAXWL; w += 2) {
+                if (w < WL) {
+                    const uint32_t mw = half ? m[w + 1] : m[w];
+                    const int base = half ? pre[w + 1] : pre[w];
+                    const int t = 32 * (w + half) + b;
+                    if (t < L) {
+                        const bool pr = (mw >> b) & 1u;
+                        const int rk = base + __popc(mw & ((1u << b) - 1u));
+                        srow[t] = pr ? (uint32_t)D.rows[item.rowoff + rk] : ABSENT;
+                    }
+                }
+            }
+            if (lane < PF) srow[L + lane] = ABSENT;
+        }
+        wave_sync_lds();
+
+        const int bd = block_coord(D, d, item.id);
+        const double c = courant(D, d, 4 * bd + ld, sp.dt);
+        const bool pos = c > 0.0;
+        const double hc = -0.5 * c;
+        const double kk = (pos ? -1.0 : 1.0) * (1.0 - 2.0 * fabs(c) / 3.0);
+
+        auto fetch = [&](int t) -> C {
+            const uint32_t sl = srow[t];
+            C v = 0;
+            if (!(sl & NEWFLAG)) {  // absent or new: zero
+                const int64_t idx = (int64_t)sl * BLK + lane;
+                if constexpr (ST == VL_F64)
+                    v = Storage<VL_F64>::load(D.pool, idx);
+                else
+                    v = Storage<ST>::loadf(D.pool, idx);
+            }
+            return v;
+        };
+
+        // pencil state
+        C a1 = 0, a2 = 0, a3 = 0;          // a(t-1), a(t-2), a(t-3)
+        C da_prev = 0;                     // slope of cell t-2
+        C face_prev = 0;                   // face t-5/2
+        double Fc_prev = 0.0, Ff_prev = 0.0;
+        double carry = 0.0;
+
+        C q[PF];
+#pragma unroll
+        for (int u = 0; u < PF; u++) q[u] = fetch(u);
+
+        for (int t0 = 0; t0 < L; t0 += PF) {
+#pragma unroll
+            for (int u = 0; u < PF; u++) {
+                const int t = t0 + u;
+                if (t < L) {
+                    const C a = q[u];
+                    q[u] = fetch(t + PF);
+                    const C da = Recon<C>::slope(a2, a1, a);
+                    const C face = a2 + (C)0.5 * (a1 - a2) - (da - da_prev) * (C)(1.0 / 6.0);
+                    C edge, dA, a6;
+                    Recon<C>::limit(a2, face_prev, face, pos, edge, dA, a6);
+                    const double Fc = c * ((double)edge + hc * ((double)dA + kk * (double)a6));
+                    const double Ff = pos ? Fc_prev : Fc;
+                    if (t >= 6) {
+                        const uint32_t sl3 = srow[t - 3];
+                        if (sl3 != ABSENT) {
+                            const int64_t idx = (int64_t)(sl3 & ~NEWFLAG) * BLK + lane;
+                            double nv;
+                            if constexpr (ST == VL_F64) {
+                                nv = (double)a3 + (Ff_prev - Ff);
+                                Storage<VL_F64>::store(D.pool, idx, nv);
+                            } else {
+                                const double x = (double)a3 + (Ff_prev - Ff) + carry;
+                                nv = Storage<ST>::round(x);
+                                carry = x - nv;
+                                Storage<ST>::store(D.pool, idx, nv);
+                            }
+                            if constexpr (LAST) {
+                                const unsigned long long any = __ballot(nv >= sp.sparse_min);
+                                const uint32_t s3 = sl3 & ~NEWFLAG;
+                                if (lane == 0 && s3 < (uint32_t)D.lcap) D.flags[s3] = any ? 1 : 0;
+                            }
+                        }
+                    }
+                    a3 = a2;
+                    a2 = a1;
+                    a1 = a;
+                    da_prev = da;
+                    face_prev = face;
+                    Fc_prev = Fc;
+                    Ff_prev = Ff;
+                }
+            }
+        }
+        if constexpr (ST != VL_F64) {
+            // terminal residual of this pencil line; ghost pencils duplicate
+            // local ones and are not counted
+            const int p = item.pencil;
+            const int t1 = sp.lo1 + p % sp.n1, t2 = sp.lo2 + p / sp.n1;
+            const bool local = t1 >= H && t1 < H + D.n[sp.e1] && t2 >= H && t2 < H + D.n[sp.e2];
+            if (local) ledger_acc += carry;
+        }
+        wave_sync_lds();
+    }
+    if constexpr (ST != VL_F64) {
+        double s = ledger_acc;
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0 && s != 0.0) atomicAdd(sp.ledger, s);
+    }
+}
+
+void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, bool last,
+                  double *ledger, hipStream_t st)
+{
+    SweepParams sp;
+    sp.d = d;
+    sp.sidx = sidx;
+    sp.L = D.P[d];
+    sp.WL = (sp.L + 31) / 32;
+    sp.e1 = (d == 0) ? 1 : 0;
+    sp.e2 = (d == 2) ? 1 : 2;
+    sp.lo1 = lo[sp.e1];
+    sp.n1 = hi[sp.e1] - lo[sp.e1];
+    sp.lo2 = lo[sp.e2];
+    sp.dt = dt;
+    sp.sparse_min = D.sparse_min;
+    sp.ledger = ledger;
+    dim3 g(2048), b(256);
+#define VL_SWEEP(ST)                                                                   \
+    do {                                                                               \
+        if (last) hipLaunchKernelGGL((k_sweep<ST, true>), g, b, 0, st, D, sp);         \
+        else hipLaunchKernelGGL((k_sweep<ST, false>), g, b, 0, st, D, sp);             \
+    } while (0)
+    switch (D.storage) {
+    case VL_F64: VL_SWEEP(VL_F64); break;
+    case VL_F32: VL_SWEEP(VL_F32); break;
+    default: VL_SWEEP(VL_BF16); break;
+    }
+#undef VL_SWEEP
+}
+
+}  // namespace vl

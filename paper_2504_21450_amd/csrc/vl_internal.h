@@ -1,0 +1,154 @@
+// Internal layout of a partition in device memory, shared by the kernels and
+// the C-ABI host code of libvlasov.so.  Not part of the public ABI.
+//
+// Device layout (all inside the caller's workspace):
+//   pool    : (lcap + gcap + 1) blocks x 64 values of the storage type.  Slots
+//             [0, lcap) belong to local cells, [lcap, lcap+gcap) to ghost
+//             cells, slot lcap+gcap is a scratch block that absorbs writes when
+//             an allocation fails (the error flag is then set).
+//   ring    : lcap int32 free local slots, a FIFO addressed by 64-bit counters
+//             (head = next to hand out, tail = next free position).
+//   cells   : per padded cell (x fastest) list start / count / capacity.
+//   lists   : block ids and slots of every cell; three regions: two for the
+//             local cells (rebuilt alternately by the end-of-step pruning) and
+//             one for the ghost cells (rebuilt by every ghost update).  Lists
+//             grow in place during a shear (new entries appended) and are
+//             sorted again by the pruning.
+//   rows    : per shear, for each (pencil, block) work item the slots of the
+//             cells of the pencil that hold the block (compacted, pencil order).
+//   items   : per shear, block id, row offset and presence mask of every item.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vlasov.h"
+
+namespace vl {
+
+constexpr int H = 3;                   // ghost depth: stencil 2 + 1 face neighbour
+constexpr int BLK = 64;                // values per velocity block (4 x 4 x 4)
+constexpr uint32_t NEWFLAG = 0x80000000u;  // row entry of a block created by growth
+constexpr int MAXL = 256;              // longest pencil (padded extent)
+constexpr int MAXWL = MAXL / 32;       // presence-mask words per item
+constexpr int NB_MAX = 131072;         // block ids per velocity mesh
+constexpr int WAVE = 64;
+
+// device error bits (Ctl::err)
+enum : unsigned long long {
+    E_RING = 1, E_GHOST_SLOTS = 2, E_LIST = 4, E_ITEMS = 8, E_ROWS = 16,
+    E_GHOST_LIST = 32, E_LOCAL_LIST = 64
+};
+
+struct Ctl {
+    unsigned long long ring_head, ring_tail, ring_limit;
+    unsigned long long ghost_top, ghost_list_top;
+    unsigned long long list_top[2];
+    unsigned long long n_items, row_top, work;
+    unsigned long long err;
+    unsigned long long upd_ps[3], read_ps[3], items[3];
+    unsigned long long pad[8];
+};
+
+struct Item {
+    int32_t id;       // velocity block id
+    int32_t pencil;   // pencil index within the shear
+    int64_t rowoff;   // first row entry
+};
+
+struct Dev {
+    int n[3], P[3], nblk[3];
+    int NB, W;               // block ids, 32-bit words of a block bitmap
+    int storage;
+    int vbuffer;
+    int64_t N, nlocal;       // padded cells, local cells
+    int64_t s[3];            // cell strides in the padded box
+    double vmin[3], dv[3], dx[3];
+    double sparse_min;
+    void *pool;
+    int64_t lcap, gcap, trash;
+    int32_t *ring;
+    uint8_t *flags;          // content flag per local slot (set by the last shear)
+    int64_t *lstart;
+    int32_t *lcount, *lcapa;
+    int32_t *lid, *lslot;
+    int64_t reg_off[3], reg_cap[3];
+    int32_t *rows;
+    int64_t row_cap;
+    Item *items;
+    uint32_t *masks;
+    int64_t item_cap;
+    int wlmax;
+    Ctl *ctl;
+    const double *cover;     // Courant override (3 x cover_stride) or null
+    int cover_stride;
+    double *cell_red;        // nlocal doubles of per-cell partial sums
+    double *red;             // small reduction scratch (>= 1024 doubles)
+    int32_t *cell_cnt;       // nlocal ints (export helper)
+};
+
+__host__ __device__ inline int64_t cell_index(const Dev &D, int x, int y, int z)
+{
+    return (int64_t)x + D.s[1] * y + D.s[2] * z;
+}
+
+__host__ __device__ inline bool is_local(const Dev &D, int x, int y, int z)
+{
+    return x >= H && x < H + D.n[0] && y >= H && y < H + D.n[1] && z >= H && z < H + D.n[2];
+}
+
+// Courant number of velocity index j along axis d: v_j dt / dx_d with the
+// cell-centre velocity v_j = vmin + (j + 1/2) dv (no fused operations, so host
+// and device agree bit for bit).
+__device__ inline double courant(const Dev &D, int d, int j, double dt)
+{
+    if (D.cover) return D.cover[d * D.cover_stride + j];
+    double v = __dadd_rn(D.vmin[d], __dmul_rn((double)j + 0.5, D.dv[d]));
+    return __ddiv_rn(__dmul_rn(v, dt), D.dx[d]);
+}
+
+__device__ inline int block_coord(const Dev &D, int d, int32_t b)
+{
+    if (d == 0) return b % D.nblk[0];
+    if (d == 1) return (b / D.nblk[0]) % D.nblk[1];
+    return b / (D.nblk[0] * D.nblk[1]);
+}
+
+// bit 0: some velocity cell of the block moves towards +d; bit 1: towards -d
+__device__ inline int block_dirs(const Dev &D, int d, int32_t b, double dt)
+{
+    int bd = block_coord(D, d, b);
+    int r = 0;
+    for (int q = 0; q < 4; q++) {
+        double c = courant(D, d, 4 * bd + q, dt);
+        r |= (c > 0.0) ? 1 : 0;
+        r |= (c < 0.0) ? 2 : 0;
+    }
+    return r;
+}
+
+// ---- launches (defined in the kernel sources, called by the host API) ----
+void launch_book(const Dev &D, int op, hipStream_t st);
+void launch_iota_ring(const Dev &D, int64_t first_free, int64_t count, hipStream_t st);
+void launch_fill(const Dev &D, const int lo[3], const int hi[3], hipStream_t st);
+void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt,
+                 hipStream_t st);
+void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, bool last,
+                  double *ledger, hipStream_t st);
+void launch_prune(const Dev &D, int nxt_region, hipStream_t st);
+void launch_cell_mass(const Dev &D, hipStream_t st);
+void launch_reduce(const Dev &D, const double *in, int64_t n, double *out, hipStream_t st);
+void launch_moments(const Dev &D, double *dn, double *dV, double *dP, hipStream_t st);
+void launch_cell_counts(const Dev &D, hipStream_t st);
+void launch_gather(const Dev &D, const int32_t *slots, int64_t n, double *out, hipStream_t st);
+
+// book-keeping operations (launch_book)
+enum {
+    BOOK_GHOST_RESET = 1,     // ghost slot and ghost list allocators to zero
+    BOOK_SWEEP_RESET = 2,     // work list counters to zero, ring limit <- tail
+    BOOK_PRUNE_RESET_A = 3,   // ring limit <- tail, local list region A allocator to zero
+    BOOK_PRUNE_RESET_B = 4,   // same for region B
+    BOOK_STEP_RESET = 5,      // per-step statistics counters to zero
+};
+
+}  // namespace vl

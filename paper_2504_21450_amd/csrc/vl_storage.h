@@ -1,0 +1,106 @@
+// Storage types of f in the block pool and their conversions.
+//   VL_F64 : double
+//   VL_F32 : float, round to nearest even from FP64
+//   VL_BF16: bfloat16 (upper half of an IEEE float), round to nearest even
+//            from FP64, done as FP64 -> FP32 rounded to odd -> BF16 to nearest
+//            even, which equals one correct rounding because FP32 carries more
+//            than two extra bits beyond BF16's precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/vlasov.h"
+
+namespace vl {
+
+__host__ __device__ inline uint32_t f32_bits(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+__host__ __device__ inline float bits_f32(uint32_t u)
+{
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+// FP64 -> FP32 rounded to odd (sticky bit in the last place)
+__device__ inline float d2f_odd(double d)
+{
+    float t = __double2float_rz(d);
+    if ((double)t != d) {
+        uint32_t u = f32_bits(t) | 1u;
+        t = bits_f32(u);
+    }
+    return t;
+}
+
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = f32_bits(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) {  // inf / nan
+        uint16_t h = (uint16_t)(u >> 16);
+        if (u & 0x007fffffu) h |= 0x40;
+        return h;
+    }
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ inline float bf16_to_f32(uint16_t h)
+{
+    return bits_f32(((uint32_t)h) << 16);
+}
+
+template <int ST>
+struct Storage;
+
+template <>
+struct Storage<VL_F64> {
+    using T = double;
+    using Word = unsigned long long;
+    static constexpr int WORDS_PER_BLOCK = 64;
+    static constexpr int BYTES = 8;
+    __device__ static double load(const void *pool, int64_t i) { return ((const double *)pool)[i]; }
+    __device__ static void store(void *pool, int64_t i, double v) { ((double *)pool)[i] = v; }
+    __device__ static double round(double v) { return v; }
+};
+
+template <>
+struct Storage<VL_F32> {
+    using T = float;
+    using Word = uint32_t;
+    static constexpr int WORDS_PER_BLOCK = 64;
+    static constexpr int BYTES = 4;
+    __device__ static double load(const void *pool, int64_t i) { return (double)((const float *)pool)[i]; }
+    __device__ static float loadf(const void *pool, int64_t i) { return ((const float *)pool)[i]; }
+    __device__ static void store(void *pool, int64_t i, double v) { ((float *)pool)[i] = (float)v; }
+    // value actually stored for v (as FP64)
+    __device__ static double round(double v) { return (double)(float)v; }
+};
+
+template <>
+struct Storage<VL_BF16> {
+    using T = uint16_t;
+    using Word = uint32_t;
+    static constexpr int WORDS_PER_BLOCK = 32;
+    static constexpr int BYTES = 2;
+    __device__ static double load(const void *pool, int64_t i)
+    {
+        return (double)bf16_to_f32(((const uint16_t *)pool)[i]);
+    }
+    __device__ static float loadf(const void *pool, int64_t i) { return bf16_to_f32(((const uint16_t *)pool)[i]); }
+    __device__ static uint16_t encode(double v) { return f32_to_bf16_rne(d2f_odd(v)); }
+    __device__ static void store(void *pool, int64_t i, double v) { ((uint16_t *)pool)[i] = encode(v); }
+    __device__ static double round(double v) { return (double)bf16_to_f32(encode(v)); }
+};
+
+inline int storage_bytes(int st) { return st == VL_F64 ? 8 : st == VL_F32 ? 4 : 2; }
+
+}  // namespace vl
