@@ -97,6 +97,10 @@ typedef struct vl_step_stats {
     int64_t updated_ps[3];/* phase-space cells written by each shear (sweep order) */
     int64_t read_ps[3];   /* phase-space cells read by each shear */
     int64_t items[3];     /* (pencil, block) work items of each shear */
+    uint64_t device_errors; /* capacity overflow bits recorded on the device (0 = none):
+                               1 free local slots, 2 ghost slots, 4 cell list,
+                               8 work items, 16 work rows, 32 ghost lists,
+                               64 local lists */
 } vl_step_stats;
 
 typedef struct vl_partition vl_partition;
@@ -166,6 +170,14 @@ int vl_export_cells(vl_partition *p, const int64_t *cells, int64_t ncells,
  * velocity index j along axis d (|values| <= 1), e.g. to drive exact integer
  * shifts; NULL restores v dt / dx.  Synchronises. */
 int vl_set_courant_override(vl_partition *p, const double *table, int32_t stride);
+
+/* Diagnostics: copy the device book-keeping counters to out[0..n) (n <= 32):
+ * [0] free-ring head, [1] free-ring tail, [2] free-ring limit, [3] ghost slots
+ * used, [4] ghost list entries used, [5..6] local list entries used (regions
+ * 0, 1), [7] work items, [8] work rows, [9] work counter, [10] error bits,
+ * [11..13] updated, [14..16] read phase-space cells, [17..19] items per shear
+ * of the last step, [20] local list region in use.  Synchronises. */
+int vl_counters(vl_partition *p, uint64_t *out, int32_t n);
 
 /* Wait for the partition's stream and report device-side errors. */
 int vl_sync(vl_partition *p);

@@ -21,7 +21,7 @@ VL_OK, VL_ERR_ARG, VL_ERR_CFL, VL_ERR_CAPACITY, VL_ERR_STALE_GHOSTS, VL_ERR_HIP,
 
 EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_fill_ghosts", "vl_translate_step",
             "vl_moments", "vl_local_block_count", "vl_export_state", "vl_export_cells",
-            "vl_set_courant_override", "vl_sync", "vl_destroy", "vl_status_string")
+            "vl_set_courant_override", "vl_counters", "vl_sync", "vl_destroy", "vl_status_string")
 
 
 class VlDesc(C.Structure):
@@ -37,7 +37,8 @@ class VlStepStats(C.Structure):
     _fields_ = [("mass_before", C.c_double), ("mass_after", C.c_double),
                 ("pruned_mass", C.c_double), ("ledger_mass", C.c_double),
                 ("local_blocks", C.c_int64), ("updated_ps", C.c_int64 * 3),
-                ("read_ps", C.c_int64 * 3), ("items", C.c_int64 * 3)]
+                ("read_ps", C.c_int64 * 3), ("items", C.c_int64 * 3),
+                ("device_errors", C.c_uint64)]
 
 
 class VlasovError(RuntimeError):
@@ -77,6 +78,8 @@ def load():
     L.vl_export_cells.argtypes = [vp, vp, i64, vp, vp, vp, i64]
     L.vl_set_courant_override.restype = C.c_int
     L.vl_set_courant_override.argtypes = [vp, vp, i32]
+    L.vl_counters.restype = C.c_int
+    L.vl_counters.argtypes = [vp, vp, i32]
     L.vl_sync.restype = C.c_int
     L.vl_sync.argtypes = [vp]
     L.vl_destroy.restype = None
@@ -130,7 +133,7 @@ class Partition:
 
     def __init__(self, n, nblk, dx, vmin, dv, offsets, ids, f, storage=VL_F64, order=(0, 1, 2),
                  sparse_min=0.0, vbuffer=0, block_capacity=None, ghost_block_capacity=None,
-                 device="cuda:0", slack=1.5):
+                 device="cuda:0", slack=2.5):
         import torch
 
         self.torch = torch
@@ -141,10 +144,18 @@ class Partition:
         ids = np.ascontiguousarray(ids, dtype=np.int32)
         f = np.ascontiguousarray(f, dtype=np.float64)
         nb = int(offsets[-1])
+        NB = int(np.prod(nblk))
+        nghost = int(np.prod([v + 6 for v in self.n])) - self.ncell
+        # small partitions get room for a dense velocity mesh (no overflow
+        # possible); large ones a multiple of the current block count
         if block_capacity is None:
             block_capacity = int(nb * slack) + 64 * self.ncell + 1024
+            if self.ncell * NB <= 4_000_000:
+                block_capacity = max(block_capacity, self.ncell * NB + 1024)
         if ghost_block_capacity is None:
             ghost_block_capacity = int(ghost_blocks_estimate(self.n, offsets) * slack) + 1024
+            if nghost * NB <= 20_000_000:
+                ghost_block_capacity = max(ghost_block_capacity, nghost * NB + 1024)
         self.desc = make_desc(n, nblk, dx, vmin, dv, order, storage, sparse_min, vbuffer,
                               block_capacity, ghost_block_capacity)
         self.ws_bytes = workspace_bytes(self.desc)
@@ -187,6 +198,8 @@ class Partition:
     def step(self, dt, mode=VL_COALESCED, stats=False):
         st = VlStepStats() if stats else None
         rc = self.lib.vl_translate_step(self.h, float(dt), int(mode), C.byref(st) if stats else None)
+        if rc != VL_OK and stats and st.device_errors:
+            raise VlasovError("vl_translate_step (device error bits %#x)" % st.device_errors, rc)
         _check("vl_translate_step", rc)
         if not stats:
             return None
@@ -208,6 +221,15 @@ class Partition:
                                  C.c_void_p(dP.data_ptr()), C.byref(tot) if total else None)
         _check("vl_moments", rc)
         return dn, dV.view(self.ncell, 3), dP.view(self.ncell, 6), tot.value
+
+    COUNTER_NAMES = ("ring_head", "ring_tail", "ring_limit", "ghost_slots", "ghost_list",
+                     "list0", "list1", "items", "rows", "work", "err", "upd0", "upd1", "upd2",
+                     "read0", "read1", "read2", "items0", "items1", "items2", "cur")
+
+    def counters(self):
+        out = np.zeros(32, np.uint64)
+        _check("vl_counters", self.lib.vl_counters(self.h, _ptr(out), 21))
+        return {k: int(v) for k, v in zip(self.COUNTER_NAMES, out)}
 
     def sync(self):
         _check("vl_sync", self.lib.vl_sync(self.h))

@@ -313,6 +313,7 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
         ctl.ring_head = 0;
         ctl.ring_tail = (unsigned long long)(D.lcap - total);
         ctl.ring_limit = ctl.ring_tail;
+        ctl.list_top[0] = (unsigned long long)run;
         if (hipMemcpy(D.ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
         if (hipMemcpy(D.lstart, lstart.data(), L.N * 8, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
         if (hipMemcpy(D.lcount, lcount.data(), L.N * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
@@ -415,7 +416,7 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
             launch_fill(D, flo, fhi, st);
         }
         launch_book(D, BOOK_SWEEP_RESET, st);
-        launch_plan(D, d, s, lo, hi, dt, st);
+        launch_plan(D, d, s, lo, hi, dt, p->cur, st);
         launch_sweep(D, d, s, lo, hi, dt, s == 2, stats ? D.red + 3 : D.red + 4, st);
     }
     const int nxt = 1 - p->cur;
@@ -451,6 +452,7 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
             stats->read_ps[s] = (int64_t)ctl.read_ps[s];
             stats->items[s] = (int64_t)ctl.items[s];
         }
+        stats->device_errors = (uint64_t)ctl.err;
         if (ctl.err) {
             p->bad = true;
             return VL_ERR_CAPACITY;
@@ -471,6 +473,20 @@ int vl_moments(vl_partition *p, double *dev_n, double *dev_V3, double *dev_P6, d
         VL_HIP(hipMemcpyAsync(host_total_mass, D.red + 5, sizeof(double), hipMemcpyDeviceToHost, p->stream));
         return device_status(p);
     }
+    return VL_OK;
+}
+
+int vl_counters(vl_partition *p, uint64_t *out, int32_t n)
+{
+    if (!p || !out || n < 0 || n > 32) return VL_ERR_ARG;
+    Ctl ctl;
+    VL_HIP(hipMemcpyAsync(&ctl, p->D.ctl, sizeof(ctl), hipMemcpyDeviceToHost, p->stream));
+    VL_HIP(hipStreamSynchronize(p->stream));
+    uint64_t v[32] = {ctl.ring_head, ctl.ring_tail, ctl.ring_limit, ctl.ghost_top, ctl.ghost_list_top,
+                      ctl.list_top[0], ctl.list_top[1], ctl.n_items, ctl.row_top, ctl.work, ctl.err,
+                      ctl.upd_ps[0], ctl.upd_ps[1], ctl.upd_ps[2], ctl.read_ps[0], ctl.read_ps[1],
+                      ctl.read_ps[2], ctl.items[0], ctl.items[1], ctl.items[2], (uint64_t)p->cur};
+    for (int i = 0; i < n; i++) out[i] = v[i];
     return VL_OK;
 }
 

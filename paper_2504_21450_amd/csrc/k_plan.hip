@@ -23,6 +23,7 @@ struct PlanParams {
     int L, WL;           // pencil length (padded extent along d), mask words
     int ulo, uhi;        // updated cells along d
     int R;               // chunk capacity (block ids per chunk)
+    int cur;             // local list region in use
     double dt;
 };
 
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     int *s_cnt = (int *)q; q += sizeof(int) * MAXL;
     int *s_cap = (int *)q; q += sizeof(int) * MAXL;
     int *s_new = (int *)q; q += sizeof(int) * MAXL;
+    int *s_req = (int *)q; q += sizeof(int) * MAXL;   // new blocks of this chunk per cell
     int *s_pre = (int *)q; q += sizeof(int) * (MAXL + 4);
     uint32_t *s_bm = (uint32_t *)q; q += sizeof(uint32_t) * W;
     int *s_rank = (int *)q; q += sizeof(int) * (W + 1);
@@ -124,6 +126,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         s_cnt[i] = D.lcount[c];
         s_cap[i] = D.lcapa[c];
         s_new[i] = 0;
+        s_req[i] = 0;
     }
     for (int w = tid; w < W; w += 256) s_bm[w] = 0u;
     __syncthreads();
@@ -208,6 +211,17 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                     rd += popc(P[w]);
                 }
             }
+            if (nnew > 0) {
+#pragma unroll
+                for (int w = 0; w < MAXWL; w++) {
+                    uint32_t g = G[w];
+                    while (g) {
+                        const int bit = __ffs(g) - 1;
+                        g &= g - 1;
+                        atomicAdd(&s_req[32 * w + bit], 1);
+                    }
+                }
+            }
             s_ai[k] = active ? 1 : 0;
             s_ro[k] = active ? rowlen : 0;
             s_np[k] = active ? nnew : 0;
@@ -216,6 +230,34 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                 st_read += rd;
                 st_items += 1;
             }
+        }
+        __syncthreads();
+        // a cell whose list cannot take this chunk's new blocks moves its
+        // list to a larger place at the end of its list region
+        for (int i = tid; i < L; i += 256) {
+            const int req = s_req[i];
+            if (req == 0) continue;
+            s_req[i] = 0;
+            const int have = s_cnt[i] + s_new[i];
+            if (have + req <= s_cap[i]) continue;
+            const int ncap = (have + req) + (have + req) / 2 + 32;
+            const int reg = local_pencil ? pp.cur : 2;
+            unsigned long long *top = local_pencil ? &D.ctl->list_top[pp.cur] : &D.ctl->ghost_list_top;
+            const unsigned long long nb0 = atomicAdd(top, (unsigned long long)ncap);
+            if ((int64_t)(nb0 + ncap) > D.reg_cap[reg]) {
+                atomicOr(&D.ctl->err, (unsigned long long)E_LIST);
+                continue;
+            }
+            const int64_t ns = D.reg_off[reg] + (int64_t)nb0;
+            for (int e = 0; e < have; e++) {
+                D.lid[ns + e] = D.lid[s_cs[i] + e];
+                D.lslot[ns + e] = D.lslot[s_cs[i] + e];
+            }
+            s_cs[i] = ns;
+            s_cap[i] = ncap;
+            const int64_t c = base + sd * i;
+            D.lstart[c] = ns;
+            D.lcapa[c] = ncap;
         }
         __syncthreads();
         const int nact = block_scan_excl(s_ai, rn, s_tmp);
@@ -347,16 +389,17 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
 
 size_t plan_lds_bytes(int W, int R, int WL)
 {
-    size_t b = sizeof(int64_t) * MAXL + sizeof(int) * MAXL * 3 + sizeof(int) * (MAXL + 4);
+    size_t b = sizeof(int64_t) * MAXL + sizeof(int) * MAXL * 4 + sizeof(int) * (MAXL + 4);
     b += sizeof(uint32_t) * W + sizeof(int) * (W + 1);
     b += (size_t)R * WL * 4 * 2 + (size_t)R * 4 + (size_t)(R + 1) * 4 * 3;
     return b + 64;
 }
 
-void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt,
+void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, int cur,
                  hipStream_t st)
 {
     PlanParams pp;
+    pp.cur = cur;
     pp.d = d;
     pp.sidx = sidx;
     pp.e1 = (d == 0) ? 1 : 0;

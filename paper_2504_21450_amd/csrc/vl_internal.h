@@ -131,7 +131,7 @@ __device__ inline int block_dirs(const Dev &D, int d, int32_t b, double dt)
 void launch_book(const Dev &D, int op, hipStream_t st);
 void launch_iota_ring(const Dev &D, int64_t first_free, int64_t count, hipStream_t st);
 void launch_fill(const Dev &D, const int lo[3], const int hi[3], hipStream_t st);
-void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt,
+void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, int cur,
                  hipStream_t st);
 void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, bool last,
                   double *ledger, hipStream_t st);
