@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of the Vlasov translation step on one MI355X.
+
+Workload (default): the sparse FP64 partition of 64 x 64 x 32 periodic
+spatial cells with a coalesced ghost domain, 100^3 velocity cells in 4^3
+blocks, one Maxwellian per cell (seeded smooth fields), blocks kept where
+max f >= 1e-15 s^3 m^-6 plus the 6 face-neighbour blocks.  A step is the whole
+path: coalesced ghost update, x, y and z shears (block growth, work list, PPM
+remap) and end-of-step pruning, plus the FP64 velocity moments.
+
+Prints one JSON line.  `value` is useful phase-space cell updates per second
+(3 x local phase-space cells per step, inputs resident in HBM), `roofline`
+describes the shear kernel (the dominant one) against the 8 TB/s HBM peak,
+and `cpu_baseline` the FP64 CPU oracle on a sub-box of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "phase-space cell updates/s per x/y/z translation step (FP32 vs FP64) + HBM GB/s"
+STORAGES = {"f64": 0, "f32": 1, "bf16": 2}
+BYTES = {"f64": 8, "f32": 4, "bf16": 2}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("k_sweep.hip", "vl_storage.h", "vl_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2504_21450_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage):
+    """HBM bytes per shear launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "shear_traffic_%s.json" % storage)
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, sample, min_seconds=10.0, max_steps=6):
+    """Time the FP64 oracle on a sub-box of the workload (explicit ghost
+    domain from the full box for the first step, then periodic)."""
+    import numpy as np
+
+    import oracle
+    from paper_2504_21450_amd import workloads as W
+
+    size = tuple(int(v) for v in sample.split("x"))
+    lo = tuple((w.n[d] - size[d]) // 2 for d in range(3))
+    cells = W.subbox_cells(w.n, lo, size, 3)
+    off, ids, f = W.take_cells(w.offsets, w.ids, w.f, cells)
+    o = oracle.OraclePartition(size, w.nblk, w.dx, w.vmin, w.dv, w.order, w.sparse_min, w.vbuffer)
+    o.load_padded(off, ids, f)
+    oracle.lib().vlo_mark_ghosts_valid(o._h)
+    local_ps = 0
+    P = tuple(s + 6 for s in size)
+    for z in range(3, 3 + size[2]):
+        for y in range(3, 3 + size[1]):
+            for x in range(3, 3 + size[0]):
+                q = x + P[0] * (y + P[1] * z)
+                local_ps += int(off[q + 1] - off[q]) * 64
+    t_steps, nsteps, useful = 0.0, 0, 0
+    while nsteps < max_steps and (t_steps < min_seconds or nsteps == 0):
+        if nsteps > 0:
+            o.fill_ghosts()
+        t0 = time.perf_counter()
+        s = o.step(w.dt)
+        t_steps += time.perf_counter() - t0
+        useful += 3 * local_ps
+        local_ps = s["blocks"] * 64
+        nsteps += 1
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": useful / t_steps, "unit": "phase-space cell updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "%s sub-box of %s, %d FP64 steps (first with the real ghost domain), %.1f s"
+                      % (sample, w.name, nsteps, t_steps)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--storage", default="f64", choices=sorted(STORAGES))
+    ap.add_argument("--mode", default="coalesced", choices=["coalesced", "per_sweep"])
+    ap.add_argument("--nx", default="64x64x32", help="local spatial box")
+    ap.add_argument("--cpu-sample", default="24x24x12")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--slack", type=float, default=1.4)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU halo exchange is a "
+              "design, not an implementation); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2504_21450_amd import binding as B
+    from paper_2504_21450_amd import workloads as W
+
+    n = tuple(int(v) for v in args.nx.split("x"))
+    t0 = time.time()
+    log("generating workload %s ..." % (n,))
+    w = W.maxwellian_sparse(n=n, threads=min(16, os.cpu_count() or 1))
+    w.storage = STORAGES[args.storage]
+    log("generated %d blocks (%.3e phase-space cells) in %.1f s"
+        % (w.nblocks, w.nblocks * 64.0, time.time() - t0))
+    mode = B.VL_COALESCED if args.mode == "coalesced" else B.VL_PER_SWEEP
+
+    p = B.Partition.from_workload(w, slack=args.slack)
+    log("partition initialised: workspace %.1f GB" % (p.ws_bytes / 1e9))
+    dn = torch.empty(p.ncell, dtype=torch.float64, device="cuda:0")
+    dV = torch.empty(p.ncell * 3, dtype=torch.float64, device="cuda:0")
+    dP = torch.empty(p.ncell * 6, dtype=torch.float64, device="cuda:0")
+    import ctypes as C
+
+    def step():
+        if mode == B.VL_COALESCED:
+            p.fill_ghosts()
+        rc = p.lib.vl_translate_step(p.h, float(w.dt), mode, None)
+        if rc:
+            raise B.VlasovError("vl_translate_step", rc)
+        rc = p.lib.vl_moments(p.h, C.c_void_p(dn.data_ptr()), C.c_void_p(dV.data_ptr()),
+                              C.c_void_p(dP.data_ptr()), None)
+        if rc:
+            raise B.VlasovError("vl_moments", rc)
+
+    for _ in range(args.warmup):
+        step()
+    p.sync()
+    log("warmup done")
+    blocks0 = p.local_blocks()
+    c0 = p.counters()
+    p.profile_start(64 * (args.steps + 1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    prof = p.profile_stop()
+    p.sync()
+    c1 = p.counters()
+    blocks1 = p.local_blocks()
+    log("timed %d steps in %.3f s" % (args.steps, elapsed))
+
+    bs = BYTES[args.storage]
+    local_ps = 0.5 * (blocks0 + blocks1) * 64
+    useful = 3 * local_ps * args.steps
+    computed = c1["cum_upd"] - c0["cum_upd"]
+    read = c1["cum_read"] - c0["cum_read"]
+    shear_ms, shear_n = prof["shear"]
+    shear_bytes = (read + computed) * bs      # algorithmic payload bytes of the shears
+    per_launch = shear_bytes / max(shear_n, 1)
+    avg_launch_s = shear_ms / max(shear_n, 1) / 1e3
+    achieved = per_launch / avg_launch_s / 1e9
+    traffic = measured_traffic(args.storage)
+
+    out = {
+        "metric": METRIC,
+        "value": useful / elapsed,
+        "unit": "phase-space cell updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": "%s coalesced-ghost sparse translation (%s storage, %s mode)"
+                               % (w.name, args.storage, args.mode),
+                   "cells": list(n), "velocity_cells": [4 * b for b in w.nblk],
+                   "local_blocks": int(blocks1), "local_ps_cells": int(blocks1 * 64),
+                   "dt_over_dx_max_courant": w.max_courant()},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sweep (PPM shear)",
+                     "algorithmic_bytes_per_launch": per_launch,
+                     "avg_launch_ms": 1e3 * avg_launch_s, "launches": shear_n},
+        "computed_updates_per_s": computed / elapsed,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a %s sub-box ..." % args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -176,8 +176,18 @@ int vl_set_courant_override(vl_partition *p, const double *table, int32_t stride
  * used, [4] ghost list entries used, [5..6] local list entries used (regions
  * 0, 1), [7] work items, [8] work rows, [9] work counter, [10] error bits,
  * [11..13] updated, [14..16] read phase-space cells, [17..19] items per shear
- * of the last step, [20] local list region in use.  Synchronises. */
+ * of the last step, [20] local list region in use, [21] updated and [22] read
+ * phase-space cells summed over all shears since init.  Synchronises. */
 int vl_counters(vl_partition *p, uint64_t *out, int32_t n);
+
+/* Diagnostics: kernel timing with HIP events recorded on the partition's
+ * stream around every launch of the ghost update, planner, shear, pruning and
+ * moment kernels, for up to max_launches launches after vl_profile_start.
+ * vl_profile_stop synchronises and returns, per class (0 ghost update,
+ * 1 planner, 2 shear, 3 pruning, 4 moments), the summed milliseconds ms[5] and
+ * the launch counts launches[5], then stops recording. */
+int vl_profile_start(vl_partition *p, int32_t max_launches);
+int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches);
 
 /* Wait for the partition's stream and report device-side errors. */
 int vl_sync(vl_partition *p);

@@ -21,7 +21,8 @@ VL_OK, VL_ERR_ARG, VL_ERR_CFL, VL_ERR_CAPACITY, VL_ERR_STALE_GHOSTS, VL_ERR_HIP,
 
 EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_fill_ghosts", "vl_translate_step",
             "vl_moments", "vl_local_block_count", "vl_export_state", "vl_export_cells",
-            "vl_set_courant_override", "vl_counters", "vl_sync", "vl_destroy", "vl_status_string")
+            "vl_set_courant_override", "vl_counters", "vl_profile_start", "vl_profile_stop",
+            "vl_sync", "vl_destroy", "vl_status_string")
 
 
 class VlDesc(C.Structure):
@@ -80,6 +81,10 @@ def load():
     L.vl_set_courant_override.argtypes = [vp, vp, i32]
     L.vl_counters.restype = C.c_int
     L.vl_counters.argtypes = [vp, vp, i32]
+    L.vl_profile_start.restype = C.c_int
+    L.vl_profile_start.argtypes = [vp, i32]
+    L.vl_profile_stop.restype = C.c_int
+    L.vl_profile_stop.argtypes = [vp, vp, vp]
     L.vl_sync.restype = C.c_int
     L.vl_sync.argtypes = [vp]
     L.vl_destroy.restype = None
@@ -224,12 +229,24 @@ class Partition:
 
     COUNTER_NAMES = ("ring_head", "ring_tail", "ring_limit", "ghost_slots", "ghost_list",
                      "list0", "list1", "items", "rows", "work", "err", "upd0", "upd1", "upd2",
-                     "read0", "read1", "read2", "items0", "items1", "items2", "cur")
+                     "read0", "read1", "read2", "items0", "items1", "items2", "cur",
+                     "cum_upd", "cum_read")
 
     def counters(self):
         out = np.zeros(32, np.uint64)
-        _check("vl_counters", self.lib.vl_counters(self.h, _ptr(out), 21))
+        _check("vl_counters", self.lib.vl_counters(self.h, _ptr(out), 23))
         return {k: int(v) for k, v in zip(self.COUNTER_NAMES, out)}
+
+    KERNEL_CLASSES = ("ghost_fill", "planner", "shear", "prune", "moments")
+
+    def profile_start(self, max_launches=4096):
+        _check("vl_profile_start", self.lib.vl_profile_start(self.h, int(max_launches)))
+
+    def profile_stop(self):
+        ms = np.zeros(5)
+        n = np.zeros(5, np.int64)
+        _check("vl_profile_stop", self.lib.vl_profile_stop(self.h, _ptr(ms), _ptr(n)))
+        return {k: (float(a), int(c)) for k, a, c in zip(self.KERNEL_CLASSES, ms, n)}
 
     def sync(self):
         _check("vl_sync", self.lib.vl_sync(self.h))

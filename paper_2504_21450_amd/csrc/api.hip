@@ -100,7 +100,15 @@ Layout make_layout(const vl_desc *d)
 
 }  // namespace
 
+struct Prof {
+    bool on = false;
+    int cap = 0, used = 0;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    std::vector<int> cls;
+};
+
 struct vl_partition {
+    Prof prof;
     vl_desc desc;
     Layout lay;
     Dev D;
@@ -125,6 +133,27 @@ int hip_ok(hipError_t e) { return e == hipSuccess ? VL_OK : VL_ERR_HIP; }
             return VL_ERR_HIP;                              \
         }                                                   \
     } while (0)
+
+// kernel classes timed by the profiler
+enum { K_FILL = 0, K_PLAN = 1, K_SWEEP = 2, K_PRUNE = 3, K_OTHER = 4, K_NCLS = 5 };
+
+struct ProfScope {
+    vl_partition *p;
+    int slot = -1;
+    ProfScope(vl_partition *pp, int c) : p(pp)
+    {
+        Prof &f = p->prof;
+        if (f.on && f.used < f.cap) {
+            slot = f.used++;
+            f.cls[slot] = c;
+            (void)hipEventRecord(f.ev[2 * slot], p->stream);
+        }
+    }
+    ~ProfScope()
+    {
+        if (slot >= 0) (void)hipEventRecord(p->prof.ev[2 * slot + 1], p->stream);
+    }
+};
 
 double host_courant(const vl_partition *p, int d, int j, double dt)
 {
@@ -323,6 +352,9 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
             if (hipMemcpy(D.lslot, lslot.data(), lslot.size() * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
         }
         if (hipMemset(D.flags, 0, (size_t)D.lcap) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        // the scratch block reads as zero in the shears
+        if (hipMemset((char *)D.pool + (size_t)D.trash * BLK * storage_bytes(d->storage), 0,
+                      (size_t)BLK * storage_bytes(d->storage)) != hipSuccess) { rc = VL_ERR_HIP; break; }
         // payload, converted to the storage type in chunks
         const int bs = storage_bytes(d->storage);
         const int64_t nval = total * BLK;
@@ -378,7 +410,10 @@ int vl_fill_ghosts(vl_partition *p)
     const Dev &D = p->D;
     int lo[3] = {0, 0, 0}, hi[3] = {D.P[0], D.P[1], D.P[2]};
     launch_book(D, BOOK_GHOST_RESET, p->stream);
-    launch_fill(D, lo, hi, p->stream);
+    {
+        ProfScope ps(p, K_FILL);
+        launch_fill(D, lo, hi, p->stream);
+    }
     VL_HIP(hipGetLastError());
     p->ghosts_valid = true;
     return VL_OK;
@@ -413,15 +448,25 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
             flo[d] = 0;
             fhi[d] = D.P[d];
             launch_book(D, BOOK_GHOST_RESET, st);
+            ProfScope ps(p, K_FILL);
             launch_fill(D, flo, fhi, st);
         }
         launch_book(D, BOOK_SWEEP_RESET, st);
-        launch_plan(D, d, s, lo, hi, dt, p->cur, st);
-        launch_sweep(D, d, s, lo, hi, dt, s == 2, stats ? D.red + 3 : D.red + 4, st);
+        {
+            ProfScope ps(p, K_PLAN);
+            launch_plan(D, d, s, lo, hi, dt, p->cur, st);
+        }
+        {
+            ProfScope ps(p, K_SWEEP);
+            launch_sweep(D, d, s, lo, hi, dt, s == 2, stats ? D.red + 3 : D.red + 4, st);
+        }
     }
     const int nxt = 1 - p->cur;
     launch_book(D, nxt == 0 ? BOOK_PRUNE_RESET_A : BOOK_PRUNE_RESET_B, st);
-    launch_prune(D, nxt, st);
+    {
+        ProfScope ps(p, K_PRUNE);
+        launch_prune(D, nxt, st);
+    }
     VL_HIP(hipGetLastError());
     p->cur = nxt;
     p->ghosts_valid = false;
@@ -466,7 +511,10 @@ int vl_moments(vl_partition *p, double *dev_n, double *dev_V3, double *dev_P6, d
     if (!p) return VL_ERR_ARG;
     if (p->bad) return VL_ERR_STATE;
     const Dev &D = p->D;
-    launch_moments(D, dev_n, dev_V3, dev_P6, p->stream);
+    {
+        ProfScope ps(p, K_OTHER);
+        launch_moments(D, dev_n, dev_V3, dev_P6, p->stream);
+    }
     VL_HIP(hipGetLastError());
     if (host_total_mass) {
         launch_reduce(D, D.cell_red, D.nlocal, D.red + 5, p->stream);
@@ -485,8 +533,46 @@ int vl_counters(vl_partition *p, uint64_t *out, int32_t n)
     uint64_t v[32] = {ctl.ring_head, ctl.ring_tail, ctl.ring_limit, ctl.ghost_top, ctl.ghost_list_top,
                       ctl.list_top[0], ctl.list_top[1], ctl.n_items, ctl.row_top, ctl.work, ctl.err,
                       ctl.upd_ps[0], ctl.upd_ps[1], ctl.upd_ps[2], ctl.read_ps[0], ctl.read_ps[1],
-                      ctl.read_ps[2], ctl.items[0], ctl.items[1], ctl.items[2], (uint64_t)p->cur};
+                      ctl.read_ps[2], ctl.items[0], ctl.items[1], ctl.items[2], (uint64_t)p->cur,
+                      ctl.cum_upd, ctl.cum_read};
     for (int i = 0; i < n; i++) out[i] = v[i];
+    return VL_OK;
+}
+
+int vl_profile_start(vl_partition *p, int32_t max_launches)
+{
+    if (!p || max_launches < 1 || max_launches > (1 << 20)) return VL_ERR_ARG;
+    Prof &f = p->prof;
+    for (hipEvent_t e : f.ev) (void)hipEventDestroy(e);
+    f.ev.assign(2 * (size_t)max_launches, nullptr);
+    f.cls.assign(max_launches, 0);
+    for (auto &e : f.ev) VL_HIP(hipEventCreate(&e));
+    f.cap = max_launches;
+    f.used = 0;
+    f.on = true;
+    return VL_OK;
+}
+
+int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches)
+{
+    if (!p || !ms || !launches) return VL_ERR_ARG;
+    Prof &f = p->prof;
+    for (int c = 0; c < K_NCLS; c++) {
+        ms[c] = 0.0;
+        launches[c] = 0;
+    }
+    VL_HIP(hipStreamSynchronize(p->stream));
+    for (int i = 0; i < f.used; i++) {
+        float t = 0.0f;
+        VL_HIP(hipEventElapsedTime(&t, f.ev[2 * i], f.ev[2 * i + 1]));
+        ms[f.cls[i]] += t;
+        launches[f.cls[i]] += 1;
+    }
+    for (hipEvent_t e : f.ev) (void)hipEventDestroy(e);
+    f.ev.clear();
+    f.cls.clear();
+    f.on = false;
+    f.cap = f.used = 0;
     return VL_OK;
 }
 
@@ -660,6 +746,11 @@ int vl_set_courant_override(vl_partition *p, const double *table, int32_t stride
     return VL_OK;
 }
 
-void vl_destroy(vl_partition *p) { delete p; }
+void vl_destroy(vl_partition *p)
+{
+    if (!p) return;
+    for (hipEvent_t e : p->prof.ev) (void)hipEventDestroy(e);
+    delete p;
+}
 
 }  // extern "C"

@@ -384,6 +384,8 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         atomicAdd(&D.ctl->upd_ps[pp.sidx], (unsigned long long)(u * BLK));
         atomicAdd(&D.ctl->read_ps[pp.sidx], (unsigned long long)(r * BLK));
         atomicAdd(&D.ctl->items[pp.sidx], (unsigned long long)n);
+        atomicAdd(&D.ctl->cum_upd, (unsigned long long)(u * BLK));
+        atomicAdd(&D.ctl->cum_read, (unsigned long long)(r * BLK));
     }
 }
 

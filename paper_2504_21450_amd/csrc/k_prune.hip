@@ -9,21 +9,36 @@
 //             back to the free ring; created blocks get zeroed slots,
 //   the list is rewritten sorted by block id into the other local list
 //             region, with fresh slack for the next step's growth.
+// The cell's list is staged through LDS in chunks so every global access is
+// coalesced and independent.
 #include "vl_internal.h"
 #include "vl_storage.h"
 
 namespace vl {
 
+constexpr int PR_CHUNK = 1024;   // list entries staged in LDS at a time
+constexpr int PR_QUEUE = 512;    // removed / created blocks queued for the wavefronts
+
 __device__ inline int popc32(uint32_t v) { return __popc(v); }
+
+template <int ST>
+__device__ inline double block_sum(const Dev &D, int64_t slot, int lane)
+{
+    double v = Storage<ST>::load(D.pool, slot * BLK + lane);
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
 
 template <int ST>
 __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_tmp[256];
+    __shared__ int32_t s_eid[PR_CHUNK], s_eslot[PR_CHUNK];
+    __shared__ int32_t s_q[PR_QUEUE];
     __shared__ double s_wmass[4];
     __shared__ unsigned long long s_base[3];
-    __shared__ int s_cnt[3];
+    __shared__ int s_cnt[4];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int W = D.W;
     uint32_t *s_old = (uint32_t *)smem;
@@ -36,55 +51,48 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
     const int cnt = D.lcount[c];
     const int64_t cs = D.lstart[c];
     const bool prune = D.sparse_min > 0.0;
+    const int nbx = D.nblk[0], nby = D.nblk[1], nbz = D.nblk[2];
 
     for (int w = tid; w < W; w += 256) {
         s_old[w] = 0u;
         s_keep[w] = 0u;
     }
-    if (tid < 3) s_cnt[tid] = 0;
+    if (tid < 4) s_cnt[tid] = 0;
     __syncthreads();
+    // old set and dilated content
     for (int e = tid; e < cnt; e += 256) {
         const int32_t id = D.lid[cs + e];
+        const int32_t slot = D.lslot[cs + e];
         atomicOr(&s_old[id >> 5], 1u << (id & 31));
-    }
-    __syncthreads();
-    if (prune) {
-        const int nbx = D.nblk[0], nby = D.nblk[1], nbz = D.nblk[2];
-        for (int e = tid; e < cnt; e += 256) {
-            const int32_t slot = D.lslot[cs + e];
-            if ((int64_t)slot >= D.lcap || !D.flags[slot]) continue;
-            const int32_t id = D.lid[cs + e];
-            const int bx = id % nbx, by = (id / nbx) % nby, bz = id / (nbx * nby);
-            for (int oz = -1; oz <= 1; oz++)
-                for (int oy = -1; oy <= 1; oy++)
-                    for (int ox = -1; ox <= 1; ox++) {
-                        const int nz = (ox != 0) + (oy != 0) + (oz != 0);
-                        if (nz > 1 && D.vbuffer != 26) continue;
-                        if (nz == 1 && D.vbuffer == 0) continue;
-                        const int xx = bx + ox, yy = by + oy, zz = bz + oz;
-                        if (xx < 0 || yy < 0 || zz < 0 || xx >= nbx || yy >= nby || zz >= nbz) continue;
-                        const int32_t nid = xx + nbx * (yy + nby * zz);
-                        atomicOr(&s_keep[nid >> 5], 1u << (nid & 31));
-                    }
+        if (!prune) {
+            atomicOr(&s_keep[id >> 5], 1u << (id & 31));
+            continue;
         }
-    } else {
-        for (int w = tid; w < W; w += 256) s_keep[w] = s_old[w];
+        if ((int64_t)slot >= D.lcap || !D.flags[slot]) continue;
+        const int bx = id % nbx, by = (id / nbx) % nby, bz = id / (nbx * nby);
+        for (int oz = -1; oz <= 1; oz++)
+            for (int oy = -1; oy <= 1; oy++)
+                for (int ox = -1; ox <= 1; ox++) {
+                    const int nz = (ox != 0) + (oy != 0) + (oz != 0);
+                    if (nz > 1 && D.vbuffer != 26) continue;
+                    if (nz == 1 && D.vbuffer == 0) continue;
+                    const int xx = bx + ox, yy = by + oy, zz = bz + oz;
+                    if (xx < 0 || yy < 0 || zz < 0 || xx >= nbx || yy >= nby || zz >= nbz) continue;
+                    const int32_t nid = xx + nbx * (yy + nby * zz);
+                    atomicOr(&s_keep[nid >> 5], 1u << (nid & 31));
+                }
     }
     __syncthreads();
-    // ranks of the kept blocks and counts
+    // ranks of the kept blocks (exclusive scan over W words) and counts
     int ncreate = 0;
-    for (int w = tid; w < W; w += 256) {
-        s_rank[w] = popc32(s_keep[w]);
-        ncreate += popc32(s_keep[w] & ~s_old[w]);
-    }
-    atomicAdd(&s_cnt[1], ncreate);
-    __syncthreads();
-    // exclusive scan of s_rank (W words) by 256 threads
     {
         const int per = (W + 255) / 256;
         const int b = min(tid * per, W), e = min(b + per, W);
         int sum = 0;
-        for (int i = b; i < e; i++) sum += s_rank[i];
+        for (int i = b; i < e; i++) {
+            sum += popc32(s_keep[i]);
+            ncreate += popc32(s_keep[i] & ~s_old[i]);
+        }
         s_tmp[tid] = sum;
         __syncthreads();
         for (int o = 1; o < 256; o <<= 1) {
@@ -95,12 +103,12 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
         }
         int run = s_tmp[tid] - sum;
         for (int i = b; i < e; i++) {
-            int v = s_rank[i];
             s_rank[i] = run;
-            run += v;
+            run += popc32(s_keep[i]);
         }
         if (tid == 255) s_cnt[0] = s_tmp[255];
     }
+    atomicAdd(&s_cnt[1], ncreate);
     __syncthreads();
     const int nkeep = s_cnt[0];
     const int ncr = s_cnt[1];
@@ -125,7 +133,6 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
         s_base[0] = lb;
         s_base[1] = rb;
         s_base[2] = ok;
-        s_cnt[2] = 0;
     }
     __syncthreads();
     if (!(s_base[2] & 1)) {
@@ -134,53 +141,77 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
     }
     const int64_t ns = D.reg_off[nxt] + (int64_t)s_base[0];
     const bool ring_failed = (s_base[2] & 2) != 0;
-
-    // old entries, one wavefront per entry: keep (move to the new list) or
-    // remove (sum its mass in FP64, return the slot to the ring)
     double wmass = 0.0;
-    for (int e = wv; e < cnt; e += 4) {
-        const int32_t id = D.lid[cs + e];
-        const int32_t slot = D.lslot[cs + e];
-        const int w = id >> 5;
-        const uint32_t bit = 1u << (id & 31);
-        if (s_keep[w] & bit) {
-            if (lane == 0) {
+
+    // old entries: kept ones move to their sorted position, removed ones are
+    // queued (slot) for the mass sum and returned to the ring
+    for (int e0 = 0; e0 < cnt; e0 += PR_CHUNK) {
+        const int m = min(PR_CHUNK, cnt - e0);
+        for (int e = tid; e < m; e += 256) {
+            s_eid[e] = D.lid[cs + e0 + e];
+            s_eslot[e] = D.lslot[cs + e0 + e];
+        }
+        if (tid == 0) s_cnt[2] = 0;
+        __syncthreads();
+        for (int e = tid; e < m; e += 256) {
+            const int32_t id = s_eid[e];
+            const int32_t slot = s_eslot[e];
+            const int w = id >> 5;
+            const uint32_t bit = 1u << (id & 31);
+            if (s_keep[w] & bit) {
                 const int pos = s_rank[w] + popc32(s_keep[w] & (bit - 1u));
                 D.lid[ns + pos] = id;
                 D.lslot[ns + pos] = slot;
-            }
-        } else {
-            double v = Storage<ST>::load(D.pool, (int64_t)slot * BLK + lane);
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            wmass += v;
-            if (lane == 0 && (int64_t)slot < D.lcap) {
-                const unsigned long long t = atomicAdd(&D.ctl->ring_tail, 1ull);
-                D.ring[(int64_t)(t % (unsigned long long)D.lcap)] = slot;
+            } else {
+                const int k = atomicAdd(&s_cnt[2], 1);
+                if (k < PR_QUEUE) s_q[k] = slot;
+                else s_eslot[e] = -1 - slot;  // summed below from the staged entries
+                if ((int64_t)slot < D.lcap) {
+                    const unsigned long long t = atomicAdd(&D.ctl->ring_tail, 1ull);
+                    D.ring[(int64_t)(t % (unsigned long long)D.lcap)] = slot;
+                }
             }
         }
+        __syncthreads();
+        const int nq = min(s_cnt[2], PR_QUEUE);
+        for (int k = wv; k < nq; k += 4) wmass += block_sum<ST>(D, s_q[k], lane);
+        if (s_cnt[2] > PR_QUEUE) {
+            // overflow of the queue: sum the rest entry by entry
+            for (int e = wv; e < m; e += 4) {
+                const int32_t sl = s_eslot[e];
+                if (sl < 0) wmass += block_sum<ST>(D, (int64_t)(-1 - sl), lane);
+            }
+        }
+        __syncthreads();
     }
-    // created blocks, one wavefront per block: take a slot, zero it
-    for (int w = 0; w < W; w++) {
-        uint32_t cr = s_keep[w] & ~s_old[w];
-        while (cr) {
-            const int bit = __ffs(cr) - 1;
-            cr &= cr - 1;
-            // block (w, bit) is handled by wave (rank % 4)
-            const int32_t id = 32 * w + bit;
-            const int pos = s_rank[w] + popc32(s_keep[w] & ((1u << bit) - 1u));
-            const int k = pos;  // distinct per created block
-            if ((k & 3) != wv) continue;
-            int ci = 0;
-            if (lane == 0) ci = atomicAdd(&s_cnt[2], 1);
-            ci = __shfl(ci, 0);
-            int64_t slot = ring_failed ? D.trash
-                                       : (int64_t)D.ring[(int64_t)((s_base[1] + ci) % (unsigned long long)D.lcap)];
-            Storage<ST>::store(D.pool, slot * BLK + lane, 0.0);
-            if (lane == 0) {
+    // created blocks: take slots, record them, zero them
+    if (ncr > 0) {
+        if (tid == 0) s_cnt[3] = 0;
+        __syncthreads();
+        const int per = (W + 255) / 256;
+        const int b = min(tid * per, W), e = min(b + per, W);
+        for (int w = b; w < e; w++) {
+            uint32_t cr = s_keep[w] & ~s_old[w];
+            while (cr) {
+                const int bit = __ffs(cr) - 1;
+                cr &= cr - 1;
+                const int32_t id = 32 * w + bit;
+                const int pos = s_rank[w] + popc32(s_keep[w] & ((1u << bit) - 1u));
+                const int ci = atomicAdd(&s_cnt[3], 1);
+                const int64_t slot = ring_failed ? D.trash
+                                                 : (int64_t)D.ring[(int64_t)((s_base[1] + ci) % (unsigned long long)D.lcap)];
                 D.lid[ns + pos] = id;
                 D.lslot[ns + pos] = (int32_t)slot;
+                if (ci < PR_QUEUE) {
+                    s_q[ci] = (int32_t)slot;
+                } else {
+                    for (int l = 0; l < BLK; l++) Storage<ST>::store(D.pool, slot * BLK + l, 0.0);
+                }
             }
         }
+        __syncthreads();
+        const int nq = min(s_cnt[3], PR_QUEUE);
+        for (int k = wv; k < nq; k += 4) Storage<ST>::store(D.pool, (int64_t)s_q[k] * BLK + lane, 0.0);
     }
     if (lane == 0) s_wmass[wv] = wmass;
     __syncthreads();

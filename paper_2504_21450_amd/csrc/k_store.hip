@@ -232,12 +232,21 @@ void launch_cell_counts(const Dev &D, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// velocity moments, FP64.  One wavefront per local cell.  Per block the wave
-// reduces sum f, sum f o and sum f o o^T with o the velocity relative to the
-// block centre (|o| <= 1.5 dv, no cancellation); blocks are then merged into
-// the cell's count / mean / scatter with the pairwise update of Chan, Golub &
-// LeVeque (1979), so the pressure tensor never subtracts large raw moments.
+// velocity moments, FP64.  One wavefront per local cell, one lane per velocity
+// cell of a block.  Sums are taken about a reference velocity R of the cell
+// (the mean centre of its blocks, which lies within a few thermal speeds of
+// the bulk velocity of the distributions used here), so the pressure tensor
+// P = m dv^3 (S2 - S1 S1^T / S0) does not subtract two large raw moments:
+//   S0 = sum f, S1 = sum f (v - R), S2 = sum f (v - R)(v - R)^T.
 // ---------------------------------------------------------------------------
+__device__ inline void block_centre(const Dev &D, int32_t b, double &cx, double &cy, double &cz)
+{
+    const int bx = b % D.nblk[0], by = (b / D.nblk[0]) % D.nblk[1], bz = b / (D.nblk[0] * D.nblk[1]);
+    cx = D.vmin[0] + (4 * bx + 2) * D.dv[0];
+    cy = D.vmin[1] + (4 * by + 2) * D.dv[1];
+    cz = D.vmin[2] + (4 * bz + 2) * D.dv[2];
+}
+
 template <int ST>
 __global__ __launch_bounds__(256) void k_moments(Dev D, double *dn, double *dV, double *dP)
 {
@@ -249,54 +258,94 @@ __global__ __launch_bounds__(256) void k_moments(Dev D, double *dn, double *dV, 
     const int64_t c = cell_index(D, x + H, y + H, z + H);
     const int cnt = D.lcount[c];
     const int64_t ls = D.lstart[c];
-    const double o0 = ((lane & 3) - 1.5) * D.dv[0];
-    const double o1 = (((lane >> 2) & 3) - 1.5) * D.dv[1];
-    const double o2 = ((lane >> 4) - 1.5) * D.dv[2];
-    double n = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
-    double M[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int e = 0; e < cnt; e++) {
-        const int32_t b = D.lid[ls + e];
-        const int64_t slot = D.lslot[ls + e];
-        const double f = Storage<ST>::load(D.pool, slot * BLK + lane);
-        double s0 = wave_sum(f);
-        if (s0 == 0.0) continue;
-        double s1x = wave_sum(f * o0), s1y = wave_sum(f * o1), s1z = wave_sum(f * o2);
-        double sxx = wave_sum(f * o0 * o0), syy = wave_sum(f * o1 * o1), szz = wave_sum(f * o2 * o2);
-        double sxy = wave_sum(f * o0 * o1), sxz = wave_sum(f * o0 * o2), syz = wave_sum(f * o1 * o2);
-        const int bx = b % D.nblk[0], by = (b / D.nblk[0]) % D.nblk[1], bz = b / (D.nblk[0] * D.nblk[1]);
-        const double cbx = D.vmin[0] + (4 * bx + 2) * D.dv[0];
-        const double cby = D.vmin[1] + (4 * by + 2) * D.dv[1];
-        const double cbz = D.vmin[2] + (4 * bz + 2) * D.dv[2];
-        const double ux = s1x / s0, uy = s1y / s0, uz = s1z / s0;  // block mean - block centre
-        const double Bxx = sxx - s1x * ux, Byy = syy - s1y * uy, Bzz = szz - s1z * uz;
-        const double Bxy = sxy - s1x * uy, Bxz = sxz - s1x * uz, Byz = syz - s1y * uz;
-        const double nn = n + s0;
-        const double dx_ = (cbx + ux) - m0, dy_ = (cby + uy) - m1, dz_ = (cbz + uz) - m2;
-        const double wgt = s0 / nn;
-        const double cw = n * wgt;  // n s0 / (n + s0)
-        m0 += dx_ * wgt;
-        m1 += dy_ * wgt;
-        m2 += dz_ * wgt;
-        M[0] += Bxx + dx_ * dx_ * cw;
-        M[1] += Byy + dy_ * dy_ * cw;
-        M[2] += Bzz + dz_ * dz_ * cw;
-        M[3] += Bxy + dx_ * dy_ * cw;
-        M[4] += Bxz + dx_ * dz_ * cw;
-        M[5] += Byz + dy_ * dz_ * cw;
-        n = nn;
+    // reference velocity: mean block centre
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    for (int e = lane; e < cnt; e += 64) {
+        double cx, cy, cz;
+        block_centre(D, D.lid[ls + e], cx, cy, cz);
+        rx += cx;
+        ry += cy;
+        rz += cz;
     }
+    rx = wave_sum(rx);
+    ry = wave_sum(ry);
+    rz = wave_sum(rz);
+    if (cnt > 0) {
+        rx /= cnt;
+        ry /= cnt;
+        rz /= cnt;
+    }
+    const double ox = ((lane & 3) - 1.5) * D.dv[0] - rx;
+    const double oy = (((lane >> 2) & 3) - 1.5) * D.dv[1] - ry;
+    const double oz = ((lane >> 4) - 1.5) * D.dv[2] - rz;
+    double s0 = 0.0, s1x = 0.0, s1y = 0.0, s1z = 0.0;
+    double sxx = 0.0, syy = 0.0, szz = 0.0, sxy = 0.0, sxz = 0.0, syz = 0.0;
+    auto acc = [&](double f, int32_t b) {
+        double cx, cy, cz;
+        block_centre(D, b, cx, cy, cz);
+        const double ux = cx + ox, uy = cy + oy, uz = cz + oz;
+        const double fx = f * ux, fy = f * uy, fz = f * uz;
+        s0 += f;
+        s1x += fx;
+        s1y += fy;
+        s1z += fz;
+        sxx += fx * ux;
+        syy += fy * uy;
+        szz += fz * uz;
+        sxy += fx * uy;
+        sxz += fx * uz;
+        syz += fy * uz;
+    };
+    int e = 0;
+    for (; e + 4 <= cnt; e += 4) {
+        const int32_t b0 = D.lid[ls + e], b1 = D.lid[ls + e + 1], b2 = D.lid[ls + e + 2], b3 = D.lid[ls + e + 3];
+        const int64_t p0 = D.lslot[ls + e], p1 = D.lslot[ls + e + 1];
+        const int64_t p2 = D.lslot[ls + e + 2], p3 = D.lslot[ls + e + 3];
+        const double f0 = Storage<ST>::load(D.pool, p0 * BLK + lane);
+        const double f1 = Storage<ST>::load(D.pool, p1 * BLK + lane);
+        const double f2 = Storage<ST>::load(D.pool, p2 * BLK + lane);
+        const double f3 = Storage<ST>::load(D.pool, p3 * BLK + lane);
+        acc(f0, b0);
+        acc(f1, b1);
+        acc(f2, b2);
+        acc(f3, b3);
+    }
+    for (; e < cnt; e++) acc(Storage<ST>::load(D.pool, (int64_t)D.lslot[ls + e] * BLK + lane), D.lid[ls + e]);
+    s0 = wave_sum(s0);
+    s1x = wave_sum(s1x);
+    s1y = wave_sum(s1y);
+    s1z = wave_sum(s1z);
+    sxx = wave_sum(sxx);
+    syy = wave_sum(syy);
+    szz = wave_sum(szz);
+    sxy = wave_sum(sxy);
+    sxz = wave_sum(sxz);
+    syz = wave_sum(syz);
     if (lane == 0) {
         const double dv3 = D.dv[0] * D.dv[1] * D.dv[2];
         const double mp = 1.67262192e-27;
-        const double nd = dv3 * n;
+        const double nd = dv3 * s0;
+        double ux = 0.0, uy = 0.0, uz = 0.0;
+        if (s0 != 0.0) {
+            ux = s1x / s0;
+            uy = s1y / s0;
+            uz = s1z / s0;
+        }
         if (dn) dn[q] = nd;
         if (dV) {
-            dV[3 * q + 0] = m0;
-            dV[3 * q + 1] = m1;
-            dV[3 * q + 2] = m2;
+            dV[3 * q + 0] = rx + ux;
+            dV[3 * q + 1] = ry + uy;
+            dV[3 * q + 2] = rz + uz;
         }
-        if (dP)
-            for (int k = 0; k < 6; k++) dP[6 * q + k] = mp * dv3 * M[k];
+        if (dP) {
+            const double k = mp * dv3;
+            dP[6 * q + 0] = k * (sxx - s1x * ux);
+            dP[6 * q + 1] = k * (syy - s1y * uy);
+            dP[6 * q + 2] = k * (szz - s1z * uz);
+            dP[6 * q + 3] = k * (sxy - s1x * uy);
+            dP[6 * q + 4] = k * (sxz - s1x * uz);
+            dP[6 * q + 5] = k * (syz - s1y * uz);
+        }
         D.cell_red[q] = nd * D.dx[0] * D.dx[1] * D.dx[2];
     }
 }

@@ -76,24 +76,130 @@ struct Recon {
 constexpr uint32_t ABSENT = 0xffffffffu;
 constexpr int PF = 8;  // cells prefetched ahead of the reconstruction front
 
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// One (pencil, block) item: march along the pencil.  DIR = +1 when every
+// lane's Courant number is positive, -1 when every one is negative, 0 when
+// the block straddles v = 0 (then the upwind side is chosen per lane).
+//
+// The reconstruction is Colella & Woodward's, written in forms with fewer
+// operations that give the same values:
+//  * limited slope: copysign(max(0, min(|c|, 2 s dl, 2 s dr)), c) with
+//    c = (a+ - a-)/2 and s = sign(c) (zero unless dl and dr share a sign);
+//  * monotonicity limiter on the face offsets dL = a - aL, dR = aR - a: the
+//    two overshoot corrections of the limiter are dL' = min(|dL|, 2|dR|) and
+//    dR' = min(|dR|, 2|dL|) (with the sign of the side), the extremum case is
+//    dL' = dR' = 0;
+//  * flux integral of the parabola over the upwind fraction |c| of the cell,
+//    expanded in dL', dR': F = c a + P dR' + Q dL' with
+//    P = c (1-c)^2, Q = c^2 (1-c) for c > 0 and P = s^2 (1-s), Q = s (1-s)^2
+//    for c = -s < 0.
+template <int ST, int DIR, bool LAST>
+__device__ __forceinline__ void march(const Dev &D, const uint32_t *srow, int L, double c, int lane,
+                                      double smin, double &carry)
+{
+    using C = typename std::conditional<ST == VL_F64, double, float>::type;  // reconstruction type
+    const bool pos = (DIR > 0) ? true : (DIR < 0) ? false : (c > 0.0);
+    const double s = fabs(c);
+    const double P = pos ? c * (1.0 - c) * (1.0 - c) : s * s * (1.0 - s);
+    const double Q = pos ? c * c * (1.0 - c) : s * (1.0 - s) * (1.0 - s);
+    const char *pool = (const char *)D.pool;
+    constexpr int BS = Storage<ST>::BYTES;
+    const uint32_t lane_off = (uint32_t)lane * BS;
+    const uint32_t zslot = (uint32_t)D.trash;  // the scratch block, all zeros
+
+    auto fetch = [&](int t) -> C {
+        uint32_t sl = uniform_u32(srow[t]);
+        sl = (sl & NEWFLAG) ? zslot : sl;  // absent or created this shear: zero
+        const char *blk = pool + (uint64_t)sl * (BLK * BS);
+        if constexpr (ST == VL_F64)
+            return *(const double *)(blk + lane_off);
+        else if constexpr (ST == VL_F32)
+            return *(const float *)(blk + lane_off);
+        else
+            return bf16_to_f32(*(const uint16_t *)(blk + lane_off));
+    };
+
+    C a1 = 0, a2 = 0, a3 = 0;   // a(t-1), a(t-2), a(t-3)
+    C da_prev = 0;              // slope of cell t-2
+    C face_prev = 0;            // face t-5/2
+    double Fc_prev = 0.0, Ff_prev = 0.0;
+    C q[PF];
+#pragma unroll
+    for (int u = 0; u < PF; u++) q[u] = fetch(u);
+    const int Lr = (L + PF - 1) / PF * PF;
+    for (int t0 = 0; t0 < Lr; t0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; u++) {
+            const int t = t0 + u;
+            const C a = q[u];
+            q[u] = fetch(t + PF);
+            // slope of cell t-1
+            const C dl = a1 - a2, dr = a - a1;
+            const C cen = (C)0.5 * (a - a2);
+            const C s2 = copysign((C)2.0, cen);
+            const C m = fmax((C)0, fmin(fmin(fabs(cen), s2 * dl), s2 * dr));
+            const C da = copysign(m, cen);
+            // face between t-2 and t-1
+            const C face = a2 + (C)0.5 * (a1 - a2) - (da - da_prev) * (C)(1.0 / 6.0);
+            // limited face offsets of cell t-2
+            const C ai = a2;
+            const C dL = ai - face_prev, dR = face - ai;
+            const C mL = fmax((C)0, fmin(fabs(dL), copysign((C)2.0, dL) * dR));
+            const C mR = fmax((C)0, fmin(fabs(dR), copysign((C)2.0, dR) * dL));
+            const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
+            const double Fc = fma(P, dRp, fma(Q, dLp, c * (double)ai));
+            const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
+            if (t >= 6 && t < L) {
+                const uint32_t sl3 = uniform_u32(srow[t - 3]);
+                if (sl3 != ABSENT) {
+                    const uint32_t s3 = sl3 & ~NEWFLAG;
+                    char *dst = (char *)D.pool + (uint64_t)s3 * (BLK * BS);
+                    double nv;
+                    if constexpr (ST == VL_F64) {
+                        nv = (double)a3 + (Ff_prev - Ff);
+                        *(double *)(dst + lane_off) = nv;
+                    } else {
+                        const double x = (double)a3 + (Ff_prev - Ff) + carry;
+                        nv = Storage<ST>::round(x);
+                        carry = x - nv;
+                        if constexpr (ST == VL_F32)
+                            *(float *)(dst + lane_off) = (float)nv;
+                        else
+                            *(uint16_t *)(dst + lane_off) = Storage<VL_BF16>::encode(nv);
+                    }
+                    if constexpr (LAST) {
+                        const unsigned long long any = __ballot(nv >= smin);
+                        if (lane == 0 && s3 < (uint32_t)D.lcap) D.flags[s3] = any ? 1 : 0;
+                    }
+                }
+            }
+            a3 = a2;
+            a2 = a1;
+            a1 = a;
+            da_prev = da;
+            face_prev = face;
+            Fc_prev = Fc;
+            Ff_prev = Ff;
+        }
+    }
+}
+
 template <int ST, bool LAST>
 __global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
 {
-    using C = typename std::conditional<ST == VL_F64, double, float>::type;  // reconstruction type
-    __shared__ uint32_t s_slot[4][MAXL + PF];
+    __shared__ uint32_t s_slot[4][MAXL + 2 * PF];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int d = sp.d, L = sp.L, WL = sp.WL;
     const int ld = (d == 0) ? (lane & 3) : (d == 1) ? ((lane >> 2) & 3) : (lane >> 4);
     const int64_t nitems = min((int64_t)D.ctl->n_items, D.item_cap);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
     uint32_t *srow = s_slot[wv];
     double ledger_acc = 0.0;
+    const int Lr = (L + PF - 1) / PF * PF;
 
-    for (;;) {
-        unsigned long long itu = 0;
-        if (lane == 0) itu = atomicAdd(&D.ctl->work, 1ull);
-        const int64_t it = (int64_t)__shfl(itu, 0);
-        if (it >= nitems) break;
+    for (int64_t it = (int64_t)blockIdx.x * 4 + wv; it < nitems; it += nwaves) {
         const Item item = D.items[it];
         // per-cell slot table of this item in LDS: slot, slot|NEWFLAG or ABSENT
         {
@@ -120,84 +226,21 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
                     }
                 }
             }
-            if (lane < PF) srow[L + lane] = ABSENT;
+            for (int t = L + lane; t < Lr + PF; t += 64) srow[t] = ABSENT;
         }
         wave_sync_lds();
 
         const int bd = block_coord(D, d, item.id);
         const double c = courant(D, d, 4 * bd + ld, sp.dt);
-        const bool pos = c > 0.0;
-        const double hc = -0.5 * c;
-        const double kk = (pos ? -1.0 : 1.0) * (1.0 - 2.0 * fabs(c) / 3.0);
-
-        auto fetch = [&](int t) -> C {
-            const uint32_t sl = srow[t];
-            C v = 0;
-            if (!(sl & NEWFLAG)) {  // absent or new: zero
-                const int64_t idx = (int64_t)sl * BLK + lane;
-                if constexpr (ST == VL_F64)
-                    v = Storage<VL_F64>::load(D.pool, idx);
-                else
-                    v = Storage<ST>::loadf(D.pool, idx);
-            }
-            return v;
-        };
-
-        // pencil state
-        C a1 = 0, a2 = 0, a3 = 0;          // a(t-1), a(t-2), a(t-3)
-        C da_prev = 0;                     // slope of cell t-2
-        C face_prev = 0;                   // face t-5/2
-        double Fc_prev = 0.0, Ff_prev = 0.0;
+        const unsigned long long npos = __ballot(c > 0.0), nneg = __ballot(c < 0.0);
         double carry = 0.0;
+        if (npos == ~0ull)
+            march<ST, 1, LAST>(D, srow, L, c, lane, sp.sparse_min, carry);
+        else if (nneg == ~0ull)
+            march<ST, -1, LAST>(D, srow, L, c, lane, sp.sparse_min, carry);
+        else
+            march<ST, 0, LAST>(D, srow, L, c, lane, sp.sparse_min, carry);
 
-        C q[PF];
-#pragma unroll
-        for (int u = 0; u < PF; u++) q[u] = fetch(u);
-
-        for (int t0 = 0; t0 < L; t0 += PF) {
-#pragma unroll
-            for (int u = 0; u < PF; u++) {
-                const int t = t0 + u;
-                if (t < L) {
-                    const C a = q[u];
-                    q[u] = fetch(t + PF);
-                    const C da = Recon<C>::slope(a2, a1, a);
-                    const C face = a2 + (C)0.5 * (a1 - a2) - (da - da_prev) * (C)(1.0 / 6.0);
-                    C edge, dA, a6;
-                    Recon<C>::limit(a2, face_prev, face, pos, edge, dA, a6);
-                    const double Fc = c * ((double)edge + hc * ((double)dA + kk * (double)a6));
-                    const double Ff = pos ? Fc_prev : Fc;
-                    if (t >= 6) {
-                        const uint32_t sl3 = srow[t - 3];
-                        if (sl3 != ABSENT) {
-                            const int64_t idx = (int64_t)(sl3 & ~NEWFLAG) * BLK + lane;
-                            double nv;
-                            if constexpr (ST == VL_F64) {
-                                nv = (double)a3 + (Ff_prev - Ff);
-                                Storage<VL_F64>::store(D.pool, idx, nv);
-                            } else {
-                                const double x = (double)a3 + (Ff_prev - Ff) + carry;
-                                nv = Storage<ST>::round(x);
-                                carry = x - nv;
-                                Storage<ST>::store(D.pool, idx, nv);
-                            }
-                            if constexpr (LAST) {
-                                const unsigned long long any = __ballot(nv >= sp.sparse_min);
-                                const uint32_t s3 = sl3 & ~NEWFLAG;
-                                if (lane == 0 && s3 < (uint32_t)D.lcap) D.flags[s3] = any ? 1 : 0;
-                            }
-                        }
-                    }
-                    a3 = a2;
-                    a2 = a1;
-                    a1 = a;
-                    da_prev = da;
-                    face_prev = face;
-                    Fc_prev = Fc;
-                    Ff_prev = Ff;
-                }
-            }
-        }
         if constexpr (ST != VL_F64) {
             // terminal residual of this pencil line; ghost pencils duplicate
             // local ones and are not counted
@@ -231,11 +274,29 @@ void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3
     sp.dt = dt;
     sp.sparse_min = D.sparse_min;
     sp.ledger = ledger;
-    dim3 g(2048), b(256);
-#define VL_SWEEP(ST)                                                                   \
-    do {                                                                               \
-        if (last) hipLaunchKernelGGL((k_sweep<ST, true>), g, b, 0, st, D, sp);         \
-        else hipLaunchKernelGGL((k_sweep<ST, false>), g, b, 0, st, D, sp);             \
+    dim3 b(256);
+    // persistent grid: exactly the workgroups that fit on the device at once,
+    // so every wavefront's share of the static item assignment runs in one round
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 256;
+    }
+    auto grid_for = [&](const void *fn) {
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1) per = 1;
+        return dim3((unsigned)(per * ncu));
+    };
+#define VL_SWEEP(ST)                                                                                      \
+    do {                                                                                                  \
+        if (last) {                                                                                       \
+            static dim3 g = grid_for((const void *)k_sweep<ST, true>);                                  \
+            hipLaunchKernelGGL((k_sweep<ST, true>), g, b, 0, st, D, sp);                                  \
+        } else {                                                                                          \
+            static dim3 g = grid_for((const void *)k_sweep<ST, false>);                                 \
+            hipLaunchKernelGGL((k_sweep<ST, false>), g, b, 0, st, D, sp);                                 \
+        }                                                                                                 \
     } while (0)
     switch (D.storage) {
     case VL_F64: VL_SWEEP(VL_F64); break;

@@ -47,7 +47,8 @@ struct Ctl {
     unsigned long long n_items, row_top, work;
     unsigned long long err;
     unsigned long long upd_ps[3], read_ps[3], items[3];
-    unsigned long long pad[8];
+    unsigned long long cum_upd, cum_read;  // never reset: totals since init
+    unsigned long long pad[6];
 };
 
 struct Item {

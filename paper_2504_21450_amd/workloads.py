@@ -171,40 +171,41 @@ def _dilate(mask, nblk, vbuffer):
 
 
 # --------------------------------------------------------------------------
-# distribution-function models (per cell parameters)
+# distribution-function models
 # --------------------------------------------------------------------------
-# A cell model is a list of components; each component is a dict with keys
-# n (m^-3), V (3,), Tpar, Tperp (K), bhat (3,). Isotropic Maxwellian:
-# Tpar == Tperp.
+# A model maps an array of local-cell indices (m,) to a list of components;
+# each component is a dict of per-cell arrays: n (m,) [m^-3], V (m, 3)
+# [m/s], Tpar, Tperp (m,) [K] and bhat (m, 3) (unit vector of the parallel
+# direction).  An isotropic Maxwellian has Tpar == Tperp; a component with
+# n = 0 is absent for that cell.
 
-def _component_f(v, comp):
-    """Analytic (bi-)Maxwellian at velocities v (..., 3)."""
-    n, V, Tpa, Tpe, bh = comp["n"], comp["V"], comp["Tpar"], comp["Tperp"], comp["bhat"]
-    u = v - V
-    upar = u @ bh
-    u2 = np.einsum("...i,...i->...", u, u)
+def _component_f(v, n, V, Tpa, Tpe, bh):
+    """(Bi-)Maxwellian at velocities v (p, 64, 3); parameters per pair (p,)."""
+    u = v - V[:, None, :]
+    upar = np.einsum("pli,pi->pl", u, bh)
+    u2 = np.einsum("pli,pli->pl", u, u)
     uperp2 = np.maximum(u2 - upar * upar, 0.0)
-    spa = K_B * Tpa / M_P
-    spe = K_B * Tpe / M_P
-    norm = n / ((2.0 * np.pi) ** 1.5 * spe * math.sqrt(spa))
-    return norm * np.exp(-0.5 * upar * upar / spa - 0.5 * uperp2 / spe)
+    spa = (K_B / M_P) * Tpa
+    spe = (K_B / M_P) * Tpe
+    norm = n / ((2.0 * np.pi) ** 1.5 * spe * np.sqrt(spa))
+    return norm[:, None] * np.exp(-0.5 * upar * upar / spa[:, None] - 0.5 * uperp2 / spe[:, None])
 
 
 def _component_radius2(comp, thresh):
-    """Squared radius (in the component's metric bound) beyond which
-    1.01 * f_component < thresh / 2 (so a sum of <= 2 components stays
-    below thresh)."""
-    spa = K_B * comp["Tpar"] / M_P
-    spe = K_B * comp["Tperp"] / M_P
-    peak = comp["n"] / ((2.0 * np.pi) ** 1.5 * spe * math.sqrt(spa))
+    """Squared radius beyond which 1.01 f_component < thresh / 2 (so a sum of
+    <= 2 components stays below thresh); -1 where the peak is too low."""
+    spa = (K_B / M_P) * comp["Tpar"]
+    spe = (K_B / M_P) * comp["Tperp"]
+    peak = comp["n"] / ((2.0 * np.pi) ** 1.5 * spe * np.sqrt(spa))
     r = 1.01 * peak / (0.5 * thresh)
-    if r <= 1.0:
-        return -1.0
-    return 2.0 * max(spa, spe) * math.log(r)
+    out = np.full(r.shape, -1.0)
+    ok = r > 1.0
+    out[ok] = 2.0 * np.maximum(spa, spe)[ok] * np.log(r[ok])
+    return out
 
 
 def sample_cells(models, nblk, vmin, dv, sparse_min, vbuffer, seed, cell_ids,
-                 threads=None, batch=64):
+                 threads=None, batch=256):
     """Sample the sparse state of the cells whose global local-cell indices are
     `cell_ids` (x-fastest numbering of the full local box).
 
@@ -221,17 +222,17 @@ def sample_cells(models, nblk, vmin, dv, sparse_min, vbuffer, seed, cell_ids,
     blo = vmin + (4 * bc + 0.5) * dv
     bhi = vmin + (4 * bc + 3.5) * dv
 
-    def values(cells_global, cell_models, pairs_cell, pairs_blk):
-        v = vmin + (4 * bc[pairs_blk][:, None, :] + lo[None, :, :] + 0.5) * dv  # (p,64,3)
+    def values(cells_global, comps, pc, pb):
+        v = vmin + (4 * bc[pb][:, None, :] + lo[None, :, :] + 0.5) * dv  # (p, 64, 3)
         fv = np.zeros(v.shape[:2])
-        # group pairs by cell to evaluate the cell's components
-        for ci in np.unique(pairs_cell):
-            sel = np.nonzero(pairs_cell == ci)[0]
-            acc = np.zeros((sel.size, 64))
-            for comp in cell_models[ci]:
-                acc += _component_f(v[sel], comp)
-            fv[sel] = acc
-        counter = ((cells_global[pairs_cell].astype(np.int64) * NB + pairs_blk)[:, None] * 64
+        for comp in comps:
+            n = comp["n"][pc]
+            sel = n > 0
+            if not np.any(sel):
+                continue
+            fv[sel] += _component_f(v[sel], n[sel], comp["V"][pc][sel], comp["Tpar"][pc][sel],
+                                    comp["Tperp"][pc][sel], comp["bhat"][pc][sel])
+        counter = ((cells_global[pc].astype(np.int64) * NB + pb)[:, None] * 64
                    + np.arange(64)[None, :])
         u = uniform_pm1(counter, seed)
         return fv * (1.0 + 0.01 * u)
@@ -239,20 +240,18 @@ def sample_cells(models, nblk, vmin, dv, sparse_min, vbuffer, seed, cell_ids,
     def do_batch(cb):
         cells_global = np.asarray(cb, dtype=np.int64)
         m = cells_global.size
-        cell_models = [models(int(c)) for c in cells_global]
+        comps = models(cells_global)
         if sparse_min > 0:
             cand = np.zeros((m, NB), dtype=bool)
-            for i, comps in enumerate(cell_models):
-                for comp in comps:
-                    r2 = _component_radius2(comp, sparse_min)
-                    if r2 < 0:
-                        continue
-                    near = np.clip(comp["V"], blo, bhi)
-                    d2 = np.sum((near - comp["V"]) ** 2, axis=1)
-                    cand[i] |= d2 <= r2
+            for comp in comps:
+                r2 = _component_radius2(comp, sparse_min)
+                V = comp["V"]
+                near = np.clip(V[:, None, :], blo[None], bhi[None])
+                d2 = np.sum((near - V[:, None, :]) ** 2, axis=2)
+                cand |= (d2 <= r2[:, None]) & (comp["n"] > 0)[:, None]
             union = cand | _dilate(cand, nblk, vbuffer)
             pc, pb = np.nonzero(union)
-            fv = values(cells_global, cell_models, pc, pb)
+            fv = values(cells_global, comps, pc, pb)
             content = np.zeros((m, NB), dtype=bool)
             content[pc, pb] = np.any(fv >= sparse_min, axis=1)
             final = _dilate(content, nblk, vbuffer)
@@ -261,7 +260,7 @@ def sample_cells(models, nblk, vmin, dv, sparse_min, vbuffer, seed, cell_ids,
         else:
             pc = np.repeat(np.arange(m), NB)
             pb = np.tile(np.arange(NB), m)
-            fv = values(cells_global, cell_models, pc, pb)
+            fv = values(cells_global, comps, pc, pb)
         counts = np.bincount(pc, minlength=m)
         return counts, pb.astype(np.int32), fv.reshape(-1)
 
@@ -283,8 +282,13 @@ def sample_cells(models, nblk, vmin, dv, sparse_min, vbuffer, seed, cell_ids,
 
 
 def _iso(n, V, T):
-    return {"n": float(n), "V": np.asarray(V, dtype=np.float64), "Tpar": float(T),
-            "Tperp": float(T), "bhat": np.array([1.0, 0.0, 0.0])}
+    """Isotropic Maxwellian component from per-cell arrays n (m,), V (m, 3), T (m,)."""
+    n = np.asarray(n, dtype=np.float64)
+    m = n.size
+    return {"n": n, "V": np.broadcast_to(np.asarray(V, dtype=np.float64), (m, 3)),
+            "Tpar": np.broadcast_to(np.asarray(T, dtype=np.float64), (m,)),
+            "Tperp": np.broadcast_to(np.asarray(T, dtype=np.float64), (m,)),
+            "bhat": np.broadcast_to(np.array([1.0, 0.0, 0.0]), (m, 3))}
 
 
 # --------------------------------------------------------------------------
@@ -302,9 +306,8 @@ def maxwellian_small(seed=21451, n=(8, 8, 8)):
     Lx = n[0] * dx[0]
 
     def model(c):
-        ix = c % n[0]
-        xc = (ix + 0.5) * dx[0]
-        return [_iso(1e6 * (1.0 + 0.2 * math.sin(2 * math.pi * xc / Lx)), (100e3, 0.0, 0.0), 1e5)]
+        xc = (c % n[0] + 0.5) * dx[0]
+        return [_iso(1e6 * (1.0 + 0.2 * np.sin(2 * np.pi * xc / Lx)), (100e3, 0.0, 0.0), 1e5)]
 
     offsets, ids, f = sample_cells(model, nblk, vmin, dv, 0.0, 0, seed,
                                    np.arange(n[0] * n[1] * n[2]))
