@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--cpu-sample", default="24x24x12")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slack", type=float, default=1.4)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, run 1 GiB device-to-device copies (a reference "
+                         "kernel for HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -200,6 +203,13 @@ def main():
         "computed_updates_per_s": computed / elapsed,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
     }
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a %s sub-box ..." % args.cpu_sample)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
