@@ -1,0 +1,109 @@
+"""The benchmark's partition at full size (64 x 64 x 32 cells, 100^3 velocity
+cells, sparse): sampled cells after one step against the oracle, which
+recomputes each sampled sub-box from the generator's input with the true
+ghost domain, and properties that hold at any size (mass ledger, Ghost
+Translation = classical refresh, FP32 error bound)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OraclePartition
+from paper_2504_21450_amd import binding as B
+from paper_2504_21450_amd import workloads as W
+from gpuhelp import need_gpu, print_case
+
+pytestmark = pytest.mark.gpu
+SUB = (4, 4, 4)
+# sub-box origins: one at the corner (its ghost domain wraps periodically), one inside
+ORIGINS = [(0, 0, 0), (30, 17, 11)]
+
+
+@pytest.fixture(scope="module")
+def full():
+    need_gpu()
+    print_case("generating the 64x64x32 sparse workload")
+    return W.maxwellian_sparse(n=(64, 64, 32), threads=16)
+
+
+def oracle_subbox_step(w, lo):
+    cells = W.subbox_cells(w.n, lo, SUB, 3)
+    off, ids, f = W.take_cells(w.offsets, w.ids, w.f, cells)
+    o = OraclePartition(SUB, w.nblk, w.dx, w.vmin, w.dv, w.order, w.sparse_min, w.vbuffer)
+    o.load_padded(off, ids, f)
+    oracle.lib().vlo_mark_ghosts_valid(o._h)
+    o.step(w.dt)
+    return o.export_local()
+
+
+def local_indices(n, lo):
+    z, y, x = np.meshgrid(*[np.arange(lo[d], lo[d] + SUB[d]) for d in (2, 1, 0)], indexing="ij")
+    return (x + n[0] * (y + n[1] * z)).reshape(-1)
+
+
+def compare_sampled(p, w, tol):
+    worst = 0.0
+    for lo in ORIGINS:
+        got = p.export_cells(local_indices(w.n, lo))
+        want = oracle_subbox_step(w, lo)
+        if tol == 0.0 or tol < 1e-10:
+            assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), "lists differ"
+            m = np.max(np.abs(want[2]))
+            err = np.max(np.abs(got[2] - want[2])) / m
+        else:
+            NB = int(np.prod(w.nblk))
+            from statehelp import to_dense
+            a, b = to_dense(*got, NB), to_dense(*want, NB)
+            err = np.max(np.abs(a - b)) / np.max(np.abs(b))
+        worst = max(worst, err)
+    assert worst <= tol, worst
+    return worst
+
+
+def test_fullsize_fp64_step_matches_oracle_on_sampled_subboxes(full):
+    w = full
+    print_case("full size FP64, coalesced, one step")
+    p = B.Partition.from_workload(w, slack=1.4)
+    p.fill_ghosts()
+    s = p.step(w.dt, B.VL_COALESCED, stats=True)
+    err = compare_sampled(p, w, 1e-12)
+    print("sampled FP64 error %.3e" % err)
+    assert abs(s["mass_after"] + s["pruned_mass"] - s["mass_before"]) <= 1e-12 * s["mass_before"]
+    # Ghost Translation computes more than the classical scheme, by the GT3
+    # box ratios of the first two shears
+    n = w.n
+    assert s["updated_ps"][0] > s["updated_ps"][2]
+    p.close()
+
+
+def test_fullsize_ghost_translation_equals_classical(full):
+    w = full
+    print_case("full size coalesced vs per-sweep, two steps")
+    a = B.Partition.from_workload(w, slack=1.4)
+    sa = []
+    for _ in range(2):
+        a.fill_ghosts()
+        sa.append(a.step(w.dt, B.VL_COALESCED, stats=True))
+    cells = np.concatenate([local_indices(w.n, lo) for lo in ORIGINS] + [np.arange(0, w.ncell, 997)])
+    ea = a.export_cells(cells)
+    a.close()
+    b = B.Partition.from_workload(w, slack=1.4)
+    sb = [b.step(w.dt, B.VL_PER_SWEEP, stats=True) for _ in range(2)]
+    eb = b.export_cells(cells)
+    b.close()
+    assert all(np.array_equal(x, y) for x, y in zip(ea, eb))
+    for x, y in zip(sa, sb):
+        assert x["mass_after"] == y["mass_after"] and x["blocks"] == y["blocks"]
+        assert x["updated_ps"][2] == y["updated_ps"][2]
+
+
+def test_fullsize_fp32_step_within_bound(full):
+    w = full
+    print_case("full size FP32, one step")
+    p = B.Partition.from_workload(w, storage=B.VL_F32, slack=1.4)
+    p.fill_ghosts()
+    s = p.step(w.dt, B.VL_COALESCED, stats=True)
+    err = compare_sampled(p, w, 1e-5)
+    print("sampled FP32 error %.3e" % err)
+    resid = s["mass_before"] - (s["mass_after"] + s["pruned_mass"] + s["ledger_mass"])
+    assert abs(resid) <= 1e-12 * s["mass_before"]
+    p.close()
