@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--cpu-sample", default="24x24x12")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slack", type=float, default=1.4)
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip the shear-kernel autotuner (it runs real steps before warmup)")
+    ap.add_argument("--variant", type=int, default=None, help="fixed shear variant (with --no-autotune)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, run 1 GiB device-to-device copies (a reference "
                          "kernel for HBM counter calibration under rocprofv3)")
@@ -146,6 +149,13 @@ def main():
         if rc:
             raise B.VlasovError("vl_moments", rc)
 
+    tune = None
+    if args.autotune:
+        best, ms = p.autotune(w.dt, mode, steps_per_variant=2)
+        tune = {"variant": best, "shear_ms_per_step": ms}
+        log("autotune: variant %d, shear ms/step per variant %s" % (best, ["%.2f" % v for v in ms]))
+    elif args.variant is not None:
+        p.set_variant(args.variant)
     for _ in range(args.warmup):
         step()
     p.sync()
@@ -202,6 +212,7 @@ def main():
                      "avg_launch_ms": 1e3 * avg_launch_s, "launches": shear_n},
         "computed_updates_per_s": computed / elapsed,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "autotune": tune,
     }
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0").fill_(1)

@@ -189,6 +189,21 @@ int vl_counters(vl_partition *p, uint64_t *out, int32_t n);
 int vl_profile_start(vl_partition *p, int32_t max_launches);
 int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches);
 
+/* Autotuner (Section 2.1's shear, kernel shapes only): runs steps_per_variant
+ * real translation steps (each with its ghost update in VL_COALESCED mode)
+ * with every compiled variant of the shear kernel (store scheme, prefetch
+ * depth, occupancy target), times the shear launches with HIP events on the
+ * partition's stream, and keeps the fastest for the following steps.  All
+ * variants compute bit-identical results, so the state advances exactly as
+ * with ordinary steps.  *best receives the chosen variant; ms_out (optional,
+ * ms_cap entries) the shear milliseconds per step of each variant.
+ * Synchronises.  Errors as vl_translate_step. */
+int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_variant, int32_t *best,
+                double *ms_out, int32_t ms_cap);
+
+/* Select a shear-kernel variant explicitly (0 .. number of variants - 1). */
+int vl_set_variant(vl_partition *p, int32_t variant);
+
 /* Wait for the partition's stream and report device-side errors. */
 int vl_sync(vl_partition *p);
 

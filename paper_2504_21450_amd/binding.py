@@ -22,7 +22,7 @@ VL_OK, VL_ERR_ARG, VL_ERR_CFL, VL_ERR_CAPACITY, VL_ERR_STALE_GHOSTS, VL_ERR_HIP,
 EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_fill_ghosts", "vl_translate_step",
             "vl_moments", "vl_local_block_count", "vl_export_state", "vl_export_cells",
             "vl_set_courant_override", "vl_counters", "vl_profile_start", "vl_profile_stop",
-            "vl_sync", "vl_destroy", "vl_status_string")
+            "vl_autotune", "vl_set_variant", "vl_sync", "vl_destroy", "vl_status_string")
 
 
 class VlDesc(C.Structure):
@@ -85,6 +85,10 @@ def load():
     L.vl_profile_start.argtypes = [vp, i32]
     L.vl_profile_stop.restype = C.c_int
     L.vl_profile_stop.argtypes = [vp, vp, vp]
+    L.vl_autotune.restype = C.c_int
+    L.vl_autotune.argtypes = [vp, dbl, i32, i32, vp, vp, i32]
+    L.vl_set_variant.restype = C.c_int
+    L.vl_set_variant.argtypes = [vp, i32]
     L.vl_sync.restype = C.c_int
     L.vl_sync.argtypes = [vp]
     L.vl_destroy.restype = None
@@ -247,6 +251,18 @@ class Partition:
         n = np.zeros(5, np.int64)
         _check("vl_profile_stop", self.lib.vl_profile_stop(self.h, _ptr(ms), _ptr(n)))
         return {k: (float(a), int(c)) for k, a, c in zip(self.KERNEL_CLASSES, ms, n)}
+
+    def autotune(self, dt, mode=VL_COALESCED, steps_per_variant=2):
+        """Time every shear-kernel variant on real steps and keep the fastest.
+        Returns (best variant, shear ms per step of each variant)."""
+        best = np.zeros(1, np.int32)
+        ms = np.full(32, np.nan)
+        _check("vl_autotune", self.lib.vl_autotune(self.h, float(dt), int(mode), int(steps_per_variant),
+                                                   _ptr(best), _ptr(ms), 32))
+        return int(best[0]), [float(v) for v in ms if not np.isnan(v)]
+
+    def set_variant(self, v):
+        _check("vl_set_variant", self.lib.vl_set_variant(self.h, int(v)))
 
     def sync(self):
         _check("vl_sync", self.lib.vl_sync(self.h))

@@ -53,7 +53,7 @@ bool desc_ok(const vl_desc *d)
     if (!isfinite(d->sparse_min)) return false;
     if (d->block_capacity < 1 || d->ghost_block_capacity < 1) return false;
     // slots (and the scratch slot) must stay below the row flag bit
-    if (d->block_capacity + d->ghost_block_capacity + 1 >= (int64_t)NEWFLAG - 1) return false;
+    if (d->block_capacity + d->ghost_block_capacity + 1 + NSINK >= (int64_t)NEWFLAG - 1) return false;
     return true;
 }
 
@@ -77,7 +77,7 @@ Layout make_layout(const vl_desc *d)
     L.cover_stride = maxnv;
     const int bs = storage_bytes(d->storage);
     size_t o = 0;
-    L.pool = o;    o = align_up(o + (size_t)(tot + 1) * BLK * bs);
+    L.pool = o;    o = align_up(o + (size_t)(tot + 1 + NSINK) * BLK * bs);  // + zero block + sinks
     L.ring = o;    o = align_up(o + (size_t)lcap * 4);
     L.flags = o;   o = align_up(o + (size_t)lcap);
     L.lstart = o;  o = align_up(o + (size_t)L.N * 8);
@@ -574,6 +574,44 @@ int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches)
     f.on = false;
     f.cap = f.used = 0;
     return VL_OK;
+}
+
+int vl_set_variant(vl_partition *p, int32_t variant)
+{
+    if (!p || variant < 0 || variant >= sweep_variants()) return VL_ERR_ARG;
+    p->D.sweep_variant = variant;
+    return VL_OK;
+}
+
+int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_variant, int32_t *best,
+                double *ms_out, int32_t ms_cap)
+{
+    if (!p || steps_per_variant < 1 || !best) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    const int nv = sweep_variants();
+    double best_ms = 0.0;
+    int best_v = 0;
+    for (int v = 0; v < nv; v++) {
+        p->D.sweep_variant = v;
+        int rc = vl_profile_start(p, 64 * steps_per_variant);
+        if (rc) return rc;
+        for (int k = 0; k < steps_per_variant; k++) {
+            if (mode == VL_COALESCED && (rc = vl_fill_ghosts(p))) return rc;
+            if ((rc = vl_translate_step(p, dt, mode, nullptr))) return rc;
+        }
+        double ms[5];
+        int64_t n[5];
+        if ((rc = vl_profile_stop(p, ms, n))) return rc;
+        const double per_step = ms[2] / steps_per_variant;  // shear kernels
+        if (ms_out && v < ms_cap) ms_out[v] = per_step;
+        if (v == 0 || per_step < best_ms) {
+            best_ms = per_step;
+            best_v = v;
+        }
+    }
+    p->D.sweep_variant = best_v;
+    *best = best_v;
+    return device_status(p);
 }
 
 int vl_sync(vl_partition *p)

@@ -141,11 +141,21 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     __syncthreads();
     const int T = s_pre[L];
 
-    // 1. union bitmap
-    for (int qf = tid; qf < T; qf += 256) {
-        const int i = find_cell(s_pre, L, qf);
-        const int32_t id = D.lid[s_cs[i] + (qf - s_pre[i])];
-        atomicOr(&s_bm[id >> 5], 1u << (id & 31));
+    // 1. union bitmap (4 independent entries per thread in flight)
+    for (int q0 = tid; q0 < T; q0 += 1024) {
+        int32_t ids[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int qf = q0 + 256 * k;
+            ids[k] = -1;
+            if (qf < T) {
+                const int i = find_cell(s_pre, L, qf);
+                ids[k] = D.lid[s_cs[i] + (qf - s_pre[i])];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (ids[k] >= 0) atomicOr(&s_bm[ids[k] >> 5], 1u << (ids[k] & 31));
     }
     __syncthreads();
     // 2. ranks
@@ -172,14 +182,31 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         for (int k = tid; k < rn * WL; k += 256) s_pres[k] = 0u;
         __syncthreads();
         // presence masks of this chunk
-        for (int qf = tid; qf < T; qf += 256) {
-            const int i = find_cell(s_pre, L, qf);
-            const int32_t id = D.lid[s_cs[i] + (qf - s_pre[i])];
-            const int w = id >> 5;
-            const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
-            if (k >= 0 && k < rn) {
-                atomicOr(&s_pres[k * WL + (i >> 5)], 1u << (i & 31));
-                s_id[k] = id;
+        for (int q0 = tid; q0 < T; q0 += 1024) {
+            int32_t ids[4];
+            int cells[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int qf = q0 + 256 * k;
+                ids[k] = -1;
+                cells[k] = 0;
+                if (qf < T) {
+                    const int i = find_cell(s_pre, L, qf);
+                    cells[k] = i;
+                    ids[k] = D.lid[s_cs[i] + (qf - s_pre[i])];
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < 4; kk++) {
+                const int32_t id = ids[kk];
+                if (id < 0) continue;
+                const int i = cells[kk];
+                const int w = id >> 5;
+                const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
+                if (k >= 0 && k < rn) {
+                    atomicOr(&s_pres[k * WL + (i >> 5)], 1u << (i & 31));
+                    s_id[k] = id;
+                }
             }
         }
         __syncthreads();
@@ -354,19 +381,38 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         }
         // rows of the blocks already held
         if (rows_ok) {
-            for (int qf = tid; qf < T; qf += 256) {
-                const int i = find_cell(s_pre, L, qf);
-                const int64_t at = s_cs[i] + (qf - s_pre[i]);
-                const int32_t id = D.lid[at];
-                const int w = id >> 5;
-                const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
-                if (k < 0 || k >= rn) continue;
-                if (s_ai[k + 1] == s_ai[k]) continue;
-                int pos = 0;
-                const int iw = i >> 5;
-                for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
-                pos += popc(s_pres[k * WL + iw] & ((1u << (i & 31)) - 1u));
-                D.rows[(int64_t)rb + s_ro[k] + pos] = D.lslot[at];
+            for (int q0 = tid; q0 < T; q0 += 1024) {
+                int32_t ids[4], sls[4];
+                int cells[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int qf = q0 + 256 * k;
+                    ids[k] = -1;
+                    cells[k] = 0;
+                    sls[k] = 0;
+                    if (qf < T) {
+                        const int i = find_cell(s_pre, L, qf);
+                        const int64_t at = s_cs[i] + (qf - s_pre[i]);
+                        cells[k] = i;
+                        ids[k] = D.lid[at];
+                        sls[k] = D.lslot[at];
+                    }
+                }
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++) {
+                    const int32_t id = ids[kk];
+                    if (id < 0) continue;
+                    const int i = cells[kk];
+                    const int w = id >> 5;
+                    const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
+                    if (k < 0 || k >= rn) continue;
+                    if (s_ai[k + 1] == s_ai[k]) continue;
+                    int pos = 0;
+                    const int iw = i >> 5;
+                    for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
+                    pos += popc(s_pres[k * WL + iw] & ((1u << (i & 31)) - 1u));
+                    D.rows[(int64_t)rb + s_ro[k] + pos] = sls[kk];
+                }
             }
         }
         __syncthreads();

@@ -38,6 +38,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
     __shared__ int32_t s_q[PR_QUEUE];
     __shared__ double s_wmass[4];
     __shared__ unsigned long long s_base[3];
+    __shared__ unsigned long long s_rbase;
     __shared__ int s_cnt[4];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int W = D.W;
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
         }
         if (err) atomicOr(&D.ctl->err, err);
         s_base[0] = lb;
-        s_base[1] = rb;
+        s_rbase = rb;
         s_base[2] = ok;
     }
     __syncthreads();
@@ -166,13 +167,36 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
                 const int k = atomicAdd(&s_cnt[2], 1);
                 if (k < PR_QUEUE) s_q[k] = slot;
                 else s_eslot[e] = -1 - slot;  // summed below from the staged entries
-                if ((int64_t)slot < D.lcap) {
-                    const unsigned long long t = atomicAdd(&D.ctl->ring_tail, 1ull);
-                    D.ring[(int64_t)(t % (unsigned long long)D.lcap)] = slot;
-                }
             }
         }
         __syncthreads();
+        // return the removed slots to the free ring: one counter update per chunk
+        {
+            const int nrem = s_cnt[2];
+            if (tid == 0 && nrem > 0) s_base[1] = atomicAdd(&D.ctl->ring_tail, (unsigned long long)nrem);
+            __syncthreads();
+            const unsigned long long t0 = s_base[1];
+            for (int k = tid; k < min(nrem, PR_QUEUE); k += 256) {
+                const int32_t slot = s_q[k];
+                D.ring[(int64_t)((t0 + k) % (unsigned long long)D.lcap)] = (int64_t)slot < D.lcap ? slot : (int32_t)D.trash;
+            }
+            if (nrem > PR_QUEUE) {
+                // queue overflow: the remaining removed slots in entry order
+                if (tid == 0) {
+                    int k = PR_QUEUE;
+                    for (int e = 0; e < m; e++) {
+                        const int32_t sl = s_eslot[e];
+                        if (sl < 0) {
+                            const int32_t slot = -1 - sl;
+                            D.ring[(int64_t)((t0 + k) % (unsigned long long)D.lcap)] =
+                                (int64_t)slot < D.lcap ? slot : (int32_t)D.trash;
+                            k++;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
         const int nq = min(s_cnt[2], PR_QUEUE);
         for (int k = wv; k < nq; k += 4) wmass += block_sum<ST>(D, s_q[k], lane);
         if (s_cnt[2] > PR_QUEUE) {
@@ -199,7 +223,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
                 const int pos = s_rank[w] + popc32(s_keep[w] & ((1u << bit) - 1u));
                 const int ci = atomicAdd(&s_cnt[3], 1);
                 const int64_t slot = ring_failed ? D.trash
-                                                 : (int64_t)D.ring[(int64_t)((s_base[1] + ci) % (unsigned long long)D.lcap)];
+                                                 : (int64_t)D.ring[(int64_t)((s_rbase + ci) % (unsigned long long)D.lcap)];
                 D.lid[ns + pos] = id;
                 D.lslot[ns + pos] = (int32_t)slot;
                 if (ci < PR_QUEUE) {

@@ -296,19 +296,18 @@ __global__ __launch_bounds__(256) void k_moments(Dev D, double *dn, double *dV, 
         sxz += fx * uz;
         syz += fy * uz;
     };
+    // 8 blocks in flight per wavefront
     int e = 0;
-    for (; e + 4 <= cnt; e += 4) {
-        const int32_t b0 = D.lid[ls + e], b1 = D.lid[ls + e + 1], b2 = D.lid[ls + e + 2], b3 = D.lid[ls + e + 3];
-        const int64_t p0 = D.lslot[ls + e], p1 = D.lslot[ls + e + 1];
-        const int64_t p2 = D.lslot[ls + e + 2], p3 = D.lslot[ls + e + 3];
-        const double f0 = Storage<ST>::load(D.pool, p0 * BLK + lane);
-        const double f1 = Storage<ST>::load(D.pool, p1 * BLK + lane);
-        const double f2 = Storage<ST>::load(D.pool, p2 * BLK + lane);
-        const double f3 = Storage<ST>::load(D.pool, p3 * BLK + lane);
-        acc(f0, b0);
-        acc(f1, b1);
-        acc(f2, b2);
-        acc(f3, b3);
+    for (; e + 8 <= cnt; e += 8) {
+        int32_t b[8];
+        double f[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            b[k] = D.lid[ls + e + k];
+            f[k] = Storage<ST>::load(D.pool, (int64_t)D.lslot[ls + e + k] * BLK + lane);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k++) acc(f[k], b[k]);
     }
     for (; e < cnt; e++) acc(Storage<ST>::load(D.pool, (int64_t)D.lslot[ls + e] * BLK + lane), D.lid[ls + e]);
     s0 = wave_sum(s0);

@@ -94,24 +94,35 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_a
 //    expanded in dL', dR': F = c a + P dR' + Q dL' with
 //    P = c (1-c)^2, Q = c^2 (1-c) for c > 0 and P = s^2 (1-s), Q = s (1-s)^2
 //    for c = -s < 0.
+// Variant "unconditional stores": slots of 8 cells at a time from LDS into
+// scalar registers; every iteration stores (to a per-wavefront sink block when
+// there is nothing to write), which keeps the compiler's memory counters exact.
 template <int ST, int DIR, bool LAST>
-__device__ __forceinline__ void march(const Dev &D, const uint32_t *srow, int L, double c, int lane,
-                                      double smin, double &carry)
+__device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, uint8_t *sflag, int L, double c,
+                                          int lane, double smin, double &carry)
 {
     using C = typename std::conditional<ST == VL_F64, double, float>::type;  // reconstruction type
     const bool pos = (DIR > 0) ? true : (DIR < 0) ? false : (c > 0.0);
     const double s = fabs(c);
     const double P = pos ? c * (1.0 - c) * (1.0 - c) : s * s * (1.0 - s);
     const double Q = pos ? c * c * (1.0 - c) : s * (1.0 - s) * (1.0 - s);
-    const char *pool = (const char *)D.pool;
     constexpr int BS = Storage<ST>::BYTES;
     const uint32_t lane_off = (uint32_t)lane * BS;
-    const uint32_t zslot = (uint32_t)D.trash;  // the scratch block, all zeros
+    const uint32_t zslot = (uint32_t)D.trash;     // all-zero block: reads of absent cells
+    // write-only block for discarded stores, one per wavefront
+    const uint32_t sink = (uint32_t)D.trash + 1 +
+                          (uint32_t)((blockIdx.x * 4 + (threadIdx.x >> 6)) % NSINK);
 
-    auto fetch = [&](int t) -> C {
-        uint32_t sl = uniform_u32(srow[t]);
-        sl = (sl & NEWFLAG) ? zslot : sl;  // absent or created this shear: zero
-        const char *blk = pool + (uint64_t)sl * (BLK * BS);
+    // slots of 8 consecutive cells (raw: slot, slot|NEWFLAG or ABSENT), wave-uniform
+    auto slots8 = [&](int t, uint32_t (&o)[PF]) {
+        const uint4 v0 = *(const uint4 *)(srow + t);
+        const uint4 v1 = *(const uint4 *)(srow + t + 4);
+        o[0] = uniform_u32(v0.x); o[1] = uniform_u32(v0.y); o[2] = uniform_u32(v0.z); o[3] = uniform_u32(v0.w);
+        o[4] = uniform_u32(v1.x); o[5] = uniform_u32(v1.y); o[6] = uniform_u32(v1.z); o[7] = uniform_u32(v1.w);
+    };
+    auto fetch = [&](uint32_t raw) -> C {
+        const uint32_t sl = (raw & NEWFLAG) ? zslot : raw;  // absent or created this shear: zero
+        const char *blk = (const char *)D.pool + (uint64_t)sl * (BLK * BS);
         if constexpr (ST == VL_F64)
             return *(const double *)(blk + lane_off);
         else if constexpr (ST == VL_F32)
@@ -124,16 +135,21 @@ __device__ __forceinline__ void march(const Dev &D, const uint32_t *srow, int L,
     C da_prev = 0;              // slope of cell t-2
     C face_prev = 0;            // face t-5/2
     double Fc_prev = 0.0, Ff_prev = 0.0;
+    uint32_t prv[PF], cur[PF], nxt[PF];
     C q[PF];
 #pragma unroll
-    for (int u = 0; u < PF; u++) q[u] = fetch(u);
+    for (int u = 0; u < PF; u++) prv[u] = ABSENT;
+    slots8(0, cur);
+#pragma unroll
+    for (int u = 0; u < PF; u++) q[u] = fetch(cur[u]);
     const int Lr = (L + PF - 1) / PF * PF;
     for (int t0 = 0; t0 < Lr; t0 += PF) {
+        slots8(t0 + PF, nxt);
 #pragma unroll
         for (int u = 0; u < PF; u++) {
             const int t = t0 + u;
             const C a = q[u];
-            q[u] = fetch(t + PF);
+            q[u] = fetch(nxt[u]);
             // slope of cell t-1
             const C dl = a1 - a2, dr = a - a1;
             const C cen = (C)0.5 * (a - a2);
@@ -143,6 +159,101 @@ __device__ __forceinline__ void march(const Dev &D, const uint32_t *srow, int L,
             // face between t-2 and t-1
             const C face = a2 + (C)0.5 * (a1 - a2) - (da - da_prev) * (C)(1.0 / 6.0);
             // limited face offsets of cell t-2
+            const C ai = a2;
+            const C dL = ai - face_prev, dR = face - ai;
+            const C mL = fmax((C)0, fmin(fabs(dL), copysign((C)2.0, dL) * dR));
+            const C mR = fmax((C)0, fmin(fabs(dR), copysign((C)2.0, dR) * dL));
+            const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
+            const double Fc = fma(P, dRp, fma(Q, dLp, c * (double)ai));
+            const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
+            // new value of cell t-3, stored unconditionally (to the sink when
+            // there is nothing to store) so the memory counters stay exact
+            const uint32_t raw3 = (u >= 3) ? cur[u - 3] : prv[u + PF - 3];
+            const bool live = (t >= 6) && (t < L) && (raw3 != ABSENT);
+            const uint32_t s3 = live ? (raw3 & ~NEWFLAG) : sink;
+            char *dst = (char *)D.pool + (uint64_t)s3 * (BLK * BS);
+            double nv;
+            if constexpr (ST == VL_F64) {
+                nv = (double)a3 + (Ff_prev - Ff);
+                *(double *)(dst + lane_off) = nv;
+            } else {
+                const double x = (double)a3 + (Ff_prev - Ff) + (live ? carry : 0.0);
+                nv = Storage<ST>::round(x);
+                if (live) carry = x - nv;
+                if constexpr (ST == VL_F32)
+                    *(float *)(dst + lane_off) = (float)nv;
+                else
+                    *(uint16_t *)(dst + lane_off) = Storage<VL_BF16>::encode(nv);
+            }
+            if constexpr (LAST) {
+                const unsigned long long any = __ballot(nv >= smin);
+                if (t >= 3) sflag[t - 3] = any ? 1 : 0;  // same value from every lane
+            }
+            a3 = a2;
+            a2 = a1;
+            a1 = a;
+            da_prev = da;
+            face_prev = face;
+            Fc_prev = Fc;
+            Ff_prev = Ff;
+        }
+#pragma unroll
+        for (int u = 0; u < PF; u++) {
+            prv[u] = cur[u];
+            cur[u] = nxt[u];
+        }
+    }
+}
+
+
+// Variant "conditional stores": the slot of each cell is read from LDS when
+// needed and the store is skipped (scalar branch) for cells without the block
+// and outside the updated range; prefetch distance PFV cells.
+template <int ST, int DIR, bool LAST, int PFV>
+__device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, uint8_t *sflag, int L, double c,
+                                           int lane, double smin, double &carry)
+{
+    using C = typename std::conditional<ST == VL_F64, double, float>::type;  // reconstruction type
+    const bool pos = (DIR > 0) ? true : (DIR < 0) ? false : (c > 0.0);
+    const double s = fabs(c);
+    const double P = pos ? c * (1.0 - c) * (1.0 - c) : s * s * (1.0 - s);
+    const double Q = pos ? c * c * (1.0 - c) : s * (1.0 - s) * (1.0 - s);
+    constexpr int BS = Storage<ST>::BYTES;
+    const uint32_t lane_off = (uint32_t)lane * BS;
+    const uint32_t zslot = (uint32_t)D.trash;
+
+    auto fetch = [&](int t) -> C {
+        uint32_t sl = uniform_u32(srow[t]);
+        sl = (sl & NEWFLAG) ? zslot : sl;
+        const char *blk = (const char *)D.pool + (uint64_t)sl * (BLK * BS);
+        if constexpr (ST == VL_F64)
+            return *(const double *)(blk + lane_off);
+        else if constexpr (ST == VL_F32)
+            return *(const float *)(blk + lane_off);
+        else
+            return bf16_to_f32(*(const uint16_t *)(blk + lane_off));
+    };
+
+    C a1 = 0, a2 = 0, a3 = 0;
+    C da_prev = 0;
+    C face_prev = 0;
+    double Fc_prev = 0.0, Ff_prev = 0.0;
+    C q[PFV];
+#pragma unroll
+    for (int u = 0; u < PFV; u++) q[u] = fetch(u);
+    const int Lr = (L + PFV - 1) / PFV * PFV;
+    for (int t0 = 0; t0 < Lr; t0 += PFV) {
+#pragma unroll
+        for (int u = 0; u < PFV; u++) {
+            const int t = t0 + u;
+            const C a = q[u];
+            q[u] = fetch(t + PFV);
+            const C dl = a1 - a2, dr = a - a1;
+            const C cen = (C)0.5 * (a - a2);
+            const C s2 = copysign((C)2.0, cen);
+            const C m = fmax((C)0, fmin(fmin(fabs(cen), s2 * dl), s2 * dr));
+            const C da = copysign(m, cen);
+            const C face = a2 + (C)0.5 * (a1 - a2) - (da - da_prev) * (C)(1.0 / 6.0);
             const C ai = a2;
             const C dL = ai - face_prev, dR = face - ai;
             const C mL = fmax((C)0, fmin(fabs(dL), copysign((C)2.0, dL) * dR));
@@ -170,7 +281,7 @@ __device__ __forceinline__ void march(const Dev &D, const uint32_t *srow, int L,
                     }
                     if constexpr (LAST) {
                         const unsigned long long any = __ballot(nv >= smin);
-                        if (lane == 0 && s3 < (uint32_t)D.lcap) D.flags[s3] = any ? 1 : 0;
+                        sflag[t - 3] = any ? 1 : 0;
                     }
                 }
             }
@@ -185,10 +296,32 @@ __device__ __forceinline__ void march(const Dev &D, const uint32_t *srow, int L,
     }
 }
 
-template <int ST, bool LAST>
-__global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
+// shear variants chosen by the autotuner (all give bit-identical results)
+//   style 0: conditional stores, style 1: unconditional stores
+//   pf: prefetch distance; minw: minimum waves per SIMD asked of the compiler (0 = default)
+struct VariantInfo {
+    int style, pf, minw;
+};
+constexpr VariantInfo VARIANTS[] = {{0, 8, 0}, {0, 8, 6}, {0, 4, 0}, {0, 16, 0},
+                                   {1, 8, 0}, {1, 8, 5}, {0, 4, 8}, {0, 8, 8}};
+constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
+
+template <int ST, int DIR, bool LAST, int V>
+__device__ __forceinline__ void march(const Dev &D, const uint32_t *srow, uint8_t *sflag, int L, double c,
+                                      int lane, double smin, double &carry)
 {
-    __shared__ uint32_t s_slot[4][MAXL + 2 * PF];
+    constexpr VariantInfo vi = VARIANTS[V];
+    if constexpr (vi.style == 1)
+        march_unc<ST, DIR, LAST>(D, srow, sflag, L, c, lane, smin, carry);
+    else
+        march_cond<ST, DIR, LAST, vi.pf>(D, srow, sflag, L, c, lane, smin, carry);
+}
+
+template <int ST, bool LAST, int V>
+__device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
+{
+    __shared__ __align__(16) uint32_t s_slot[4][MAXL + 48];
+    __shared__ uint8_t s_flag[4][MAXL + 48];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int d = sp.d, L = sp.L, WL = sp.WL;
@@ -226,7 +359,7 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
                     }
                 }
             }
-            for (int t = L + lane; t < Lr + PF; t += 64) srow[t] = ABSENT;
+            for (int t = L + lane; t < L + 40; t += 64) srow[t] = ABSENT;
         }
         wave_sync_lds();
 
@@ -234,12 +367,22 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
         const double c = courant(D, d, 4 * bd + ld, sp.dt);
         const unsigned long long npos = __ballot(c > 0.0), nneg = __ballot(c < 0.0);
         double carry = 0.0;
+        uint8_t *sflag = s_flag[wv];
         if (npos == ~0ull)
-            march<ST, 1, LAST>(D, srow, L, c, lane, sp.sparse_min, carry);
+            march<ST, 1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry);
         else if (nneg == ~0ull)
-            march<ST, -1, LAST>(D, srow, L, c, lane, sp.sparse_min, carry);
+            march<ST, -1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry);
         else
-            march<ST, 0, LAST>(D, srow, L, c, lane, sp.sparse_min, carry);
+            march<ST, 0, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry);
+        if constexpr (LAST) {
+            // content flags of the written cells, one store per cell in parallel
+            wave_sync_lds();
+            for (int t = 3 + lane; t < L - 3; t += 64) {
+                const uint32_t raw = srow[t];
+                const uint32_t sl = raw & ~NEWFLAG;
+                if (raw != ABSENT && sl < (uint32_t)D.lcap) D.flags[sl] = sflag[t];
+            }
+        }
 
         if constexpr (ST != VL_F64) {
             // terminal residual of this pencil line; ghost pencils duplicate
@@ -258,6 +401,65 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
     }
 }
 
+template <int ST, bool LAST, int V>
+__global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
+{
+    sweep_body<ST, LAST, V>(D, sp);
+}
+
+template <int ST, bool LAST, int V, int MINW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW))) void k_sweep_occ(Dev D, SweepParams sp)
+{
+    sweep_body<ST, LAST, V>(D, sp);
+}
+
+template <typename K>
+static dim3 persistent_grid(K kernel)
+{
+    // exactly the workgroups that fit on the device at once, so every
+    // wavefront's share of the static item assignment runs in one round
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 256;
+    }
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per < 1) per = 1;
+    return dim3((unsigned)(per * ncu));
+}
+
+template <int ST, bool LAST, int V>
+static void launch_variant(const Dev &D, const SweepParams &sp, hipStream_t st)
+{
+    constexpr VariantInfo vi = VARIANTS[V];
+    if constexpr (vi.minw > 0) {
+        static const dim3 g = persistent_grid(k_sweep_occ<ST, LAST, V, (vi.minw > 0 ? vi.minw : 1)>);
+        hipLaunchKernelGGL((k_sweep_occ<ST, LAST, V, (vi.minw > 0 ? vi.minw : 1)>), g, dim3(256), 0, st, D, sp);
+    } else {
+        static const dim3 g = persistent_grid(k_sweep<ST, LAST, V>);
+        hipLaunchKernelGGL((k_sweep<ST, LAST, V>), g, dim3(256), 0, st, D, sp);
+    }
+}
+
+template <int ST, bool LAST>
+static void launch_st(const Dev &D, const SweepParams &sp, int v, hipStream_t st)
+{
+    switch (v) {
+    case 1: launch_variant<ST, LAST, 1>(D, sp, st); break;
+    case 2: launch_variant<ST, LAST, 2>(D, sp, st); break;
+    case 3: launch_variant<ST, LAST, 3>(D, sp, st); break;
+    case 4: launch_variant<ST, LAST, 4>(D, sp, st); break;
+    case 5: launch_variant<ST, LAST, 5>(D, sp, st); break;
+    case 6: launch_variant<ST, LAST, 6>(D, sp, st); break;
+    case 7: launch_variant<ST, LAST, 7>(D, sp, st); break;
+    default: launch_variant<ST, LAST, 0>(D, sp, st); break;
+    }
+}
+
+int sweep_variants() { return NVARIANTS; }
+
 void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, bool last,
                   double *ledger, hipStream_t st)
 {
@@ -274,36 +476,12 @@ void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3
     sp.dt = dt;
     sp.sparse_min = D.sparse_min;
     sp.ledger = ledger;
-    dim3 b(256);
-    // persistent grid: exactly the workgroups that fit on the device at once,
-    // so every wavefront's share of the static item assignment runs in one round
-    static int ncu = 0;
-    if (ncu == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            ncu = 256;
-    }
-    auto grid_for = [&](const void *fn) {
-        int per = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1) per = 1;
-        return dim3((unsigned)(per * ncu));
-    };
-#define VL_SWEEP(ST)                                                                                      \
-    do {                                                                                                  \
-        if (last) {                                                                                       \
-            static dim3 g = grid_for((const void *)k_sweep<ST, true>);                                  \
-            hipLaunchKernelGGL((k_sweep<ST, true>), g, b, 0, st, D, sp);                                  \
-        } else {                                                                                          \
-            static dim3 g = grid_for((const void *)k_sweep<ST, false>);                                 \
-            hipLaunchKernelGGL((k_sweep<ST, false>), g, b, 0, st, D, sp);                                 \
-        }                                                                                                 \
-    } while (0)
+    const int v = (D.sweep_variant >= 0 && D.sweep_variant < NVARIANTS) ? D.sweep_variant : 0;
     switch (D.storage) {
-    case VL_F64: VL_SWEEP(VL_F64); break;
-    case VL_F32: VL_SWEEP(VL_F32); break;
-    default: VL_SWEEP(VL_BF16); break;
+    case VL_F64: last ? launch_st<VL_F64, true>(D, sp, v, st) : launch_st<VL_F64, false>(D, sp, v, st); break;
+    case VL_F32: last ? launch_st<VL_F32, true>(D, sp, v, st) : launch_st<VL_F32, false>(D, sp, v, st); break;
+    default: last ? launch_st<VL_BF16, true>(D, sp, v, st) : launch_st<VL_BF16, false>(D, sp, v, st); break;
     }
-#undef VL_SWEEP
 }
 
 }  // namespace vl

@@ -2,10 +2,13 @@
 // the C-ABI host code of libvlasov.so.  Not part of the public ABI.
 //
 // Device layout (all inside the caller's workspace):
-//   pool    : (lcap + gcap + 1) blocks x 64 values of the storage type.  Slots
-//             [0, lcap) belong to local cells, [lcap, lcap+gcap) to ghost
-//             cells, slot lcap+gcap is a scratch block that absorbs writes when
-//             an allocation fails (the error flag is then set).
+//   pool    : (lcap + gcap + 1 + NSINK) blocks x 64 values of the storage type.
+//             Slots [0, lcap) belong to local cells, [lcap, lcap+gcap) to ghost
+//             cells; slot lcap+gcap is an all-zero block (what the shears read
+//             for a cell without the block; also handed out, with the error flag
+//             set, when an allocation fails) and the NSINK slots after it are
+//             write-only sinks for the shears' discarded stores, one per
+//             resident wavefront so the stores spread over the memory channels.
 //   ring    : lcap int32 free local slots, a FIFO addressed by 64-bit counters
 //             (head = next to hand out, tail = next free position).
 //   cells   : per padded cell (x fastest) list start / count / capacity.
@@ -33,6 +36,7 @@ constexpr int MAXL = 256;              // longest pencil (padded extent)
 constexpr int MAXWL = MAXL / 32;       // presence-mask words per item
 constexpr int NB_MAX = 131072;         // block ids per velocity mesh
 constexpr int WAVE = 64;
+constexpr int NSINK = 8192;            // sink blocks (>= resident wavefronts)
 
 // device error bits (Ctl::err)
 enum : unsigned long long {
@@ -86,6 +90,7 @@ struct Dev {
     double *cell_red;        // nlocal doubles of per-cell partial sums
     double *red;             // small reduction scratch (>= 1024 doubles)
     int32_t *cell_cnt;       // nlocal ints (export helper)
+    int sweep_variant;       // shear kernel variant (autotuner)
 };
 
 __host__ __device__ inline int64_t cell_index(const Dev &D, int x, int y, int z)
@@ -134,6 +139,7 @@ void launch_iota_ring(const Dev &D, int64_t first_free, int64_t count, hipStream
 void launch_fill(const Dev &D, const int lo[3], const int hi[3], hipStream_t st);
 void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, int cur,
                  hipStream_t st);
+int sweep_variants();
 void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, bool last,
                   double *ledger, hipStream_t st);
 void launch_prune(const Dev &D, int nxt_region, hipStream_t st);

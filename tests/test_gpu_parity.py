@@ -172,3 +172,31 @@ def test_capacity_overflow_is_reported():
         p.step(1.0, stats=True)
     assert e.value.status == B.VL_ERR_CAPACITY
     assert p.step_rc(1.0, B.VL_PER_SWEEP) == B.VL_ERR_STATE
+
+
+def test_all_shear_variants_and_autotuner_are_bit_identical(sparse_small):
+    """Every compiled shear variant (store scheme, prefetch depth, occupancy)
+    gives the same state bit for bit, so the autotuner's real steps leave the
+    trajectory unchanged."""
+    w = sparse_small
+    print_case("shear variants")
+    ref = gpu_partition(w)
+    run_gpu(ref, w.dt, 2)
+    want = ref.export()
+    nvar = 0
+    for v in range(64):
+        p = gpu_partition(w)
+        try:
+            p.set_variant(v)
+        except B.VlasovError:
+            break
+        nvar += 1
+        run_gpu(p, w.dt, 2)
+        assert all(np.array_equal(x, y) for x, y in zip(p.export(), want)), v
+    assert nvar >= 4
+    a = gpu_partition(w)
+    best, ms = a.autotune(w.dt, B.VL_COALESCED, steps_per_variant=1)
+    assert 0 <= best < nvar and len(ms) == nvar
+    b = gpu_partition(w)
+    run_gpu(b, w.dt, nvar)
+    assert all(np.array_equal(x, y) for x, y in zip(a.export(), b.export()))
