@@ -213,7 +213,13 @@ def main():
         "computed_updates_per_s": computed / elapsed,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
         "autotune": tune,
+        "per_shear": [{"axis": "xyz"[w.order[s]],
+                       "ms": prof["shear%d" % (s + 1)][0] / max(prof["shear%d" % (s + 1)][1], 1),
+                       "algorithmic_gb": (c1["upd%d" % s] + c1["read%d" % s]) * bs / 1e9,
+                       "items": c1["items%d" % s]} for s in range(3)],
     }
+    for s in out["per_shear"]:
+        s["gbs"] = s["algorithmic_gb"] / (s["ms"] / 1e3) if s["ms"] > 0 else None
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0").fill_(1)
         dst = torch.empty_like(src)

@@ -184,8 +184,9 @@ int vl_counters(vl_partition *p, uint64_t *out, int32_t n);
  * stream around every launch of the ghost update, planner, shear, pruning and
  * moment kernels, for up to max_launches launches after vl_profile_start.
  * vl_profile_stop synchronises and returns, per class (0 ghost update,
- * 1 planner, 2 shear, 3 pruning, 4 moments), the summed milliseconds ms[5] and
- * the launch counts launches[5], then stops recording. */
+ * 1 planner, 2 shears (all), 3 pruning, 4 moments, 5/6/7 first/second/third
+ * shear of the step), the summed milliseconds ms[8] and the launch counts
+ * launches[8], then stops recording. */
 int vl_profile_start(vl_partition *p, int32_t max_launches);
 int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches);
 

@@ -135,7 +135,7 @@ int hip_ok(hipError_t e) { return e == hipSuccess ? VL_OK : VL_ERR_HIP; }
     } while (0)
 
 // kernel classes timed by the profiler
-enum { K_FILL = 0, K_PLAN = 1, K_SWEEP = 2, K_PRUNE = 3, K_OTHER = 4, K_NCLS = 5 };
+enum { K_FILL = 0, K_PLAN = 1, K_SWEEP = 2, K_PRUNE = 3, K_OTHER = 4, K_SHEAR0 = 5, K_NCLS = 8 };
 
 struct ProfScope {
     vl_partition *p;
@@ -457,7 +457,7 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
             launch_plan(D, d, s, lo, hi, dt, p->cur, st);
         }
         {
-            ProfScope ps(p, K_SWEEP);
+            ProfScope ps(p, K_SHEAR0 + s);
             launch_sweep(D, d, s, lo, hi, dt, s == 2, stats ? D.red + 3 : D.red + 4, st);
         }
     }
@@ -567,6 +567,10 @@ int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches)
         VL_HIP(hipEventElapsedTime(&t, f.ev[2 * i], f.ev[2 * i + 1]));
         ms[f.cls[i]] += t;
         launches[f.cls[i]] += 1;
+        if (f.cls[i] >= K_SHEAR0) {  // all shears together as well
+            ms[K_SWEEP] += t;
+            launches[K_SWEEP] += 1;
+        }
     }
     for (hipEvent_t e : f.ev) (void)hipEventDestroy(e);
     f.ev.clear();
@@ -599,8 +603,8 @@ int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_vari
             if (mode == VL_COALESCED && (rc = vl_fill_ghosts(p))) return rc;
             if ((rc = vl_translate_step(p, dt, mode, nullptr))) return rc;
         }
-        double ms[5];
-        int64_t n[5];
+        double ms[K_NCLS];
+        int64_t n[K_NCLS];
         if ((rc = vl_profile_stop(p, ms, n))) return rc;
         const double per_step = ms[2] / steps_per_variant;  // shear kernels
         if (ms_out && v < ms_cap) ms_out[v] = per_step;

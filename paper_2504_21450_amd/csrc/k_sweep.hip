@@ -297,13 +297,15 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
 }
 
 // shear variants chosen by the autotuner (all give bit-identical results)
-//   style 0: conditional stores, style 1: unconditional stores
+//   style 0: conditional stores, style 1: unconditional stores, style 2:
+//   conditional stores with the items of a wavefront streamed (the next
+//   item's slot table and first cells are loaded during the current item)
 //   pf: prefetch distance; minw: minimum waves per SIMD asked of the compiler (0 = default)
 struct VariantInfo {
     int style, pf, minw;
 };
-constexpr VariantInfo VARIANTS[] = {{0, 8, 0}, {0, 8, 6}, {0, 4, 0}, {0, 16, 0},
-                                   {1, 8, 0}, {1, 8, 5}, {0, 4, 8}, {0, 8, 8}};
+constexpr VariantInfo VARIANTS[] = {{0, 8, 0}, {0, 8, 6}, {0, 4, 0}, {0, 16, 0}, {1, 8, 0}, {1, 8, 5},
+                                   {2, 8, 0}, {0, 4, 8}, {0, 8, 8}, {2, 8, 8}};
 constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 
 template <int ST, int DIR, bool LAST, int V>
@@ -401,16 +403,226 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// streamed items (style 2)
+// ---------------------------------------------------------------------------
+// Build the per-cell slot table of item `it` into srow[0 .. L+40).
+__device__ __forceinline__ void build_slots(const Dev &D, int64_t it, int64_t nitems, int L, int WL, int lane,
+                                            uint32_t *srow)
+{
+    if (it >= nitems) {
+        for (int t = lane; t < L + 40; t += 64) srow[t] = ABSENT;
+        return;
+    }
+    const Item item = D.items[it];
+    uint32_t m[MAXWL];
+    int pre[MAXWL + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int w = 0; w < MAXWL; w++) {
+        m[w] = (w < WL) ? D.masks[it * D.wlmax + w] : 0u;
+        pre[w + 1] = pre[w] + __popc(m[w]);
+    }
+    const int half = lane >> 5, b = lane & 31;
+#pragma unroll
+    for (int w = 0; w < MAXWL; w += 2) {
+        if (w < WL) {
+            const uint32_t mw = half ? m[w + 1] : m[w];
+            const int base = half ? pre[w + 1] : pre[w];
+            const int t = 32 * (w + half) + b;
+            if (t < L) {
+                const bool pr = (mw >> b) & 1u;
+                const int rk = base + __popc(mw & ((1u << b) - 1u));
+                srow[t] = pr ? (uint32_t)D.rows[item.rowoff + rk] : ABSENT;
+            }
+        }
+    }
+    for (int t = L + lane; t < L + 40; t += 64) srow[t] = ABSENT;
+}
+
+// One item of the stream: cells of X; q holds X's first 8 values on entry and
+// the next item's (table Y) first 8 on exit.  build_next() fills Y.
+template <int ST, int DIR, bool LAST, typename BUILD>
+__device__ __forceinline__ void march_stream(const Dev &D, const uint32_t *X, const uint32_t *Y, uint8_t *sflag,
+                                             int L, double c, int lane, double smin, double &carry,
+                                             typename std::conditional<ST == VL_F64, double, float>::type (&q)[8],
+                                             BUILD build_next)
+{
+    using C = typename std::conditional<ST == VL_F64, double, float>::type;
+    const bool pos = (DIR > 0) ? true : (DIR < 0) ? false : (c > 0.0);
+    const double s = fabs(c);
+    const double P = pos ? c * (1.0 - c) * (1.0 - c) : s * s * (1.0 - s);
+    const double Q = pos ? c * c * (1.0 - c) : s * (1.0 - s) * (1.0 - s);
+    constexpr int BS = Storage<ST>::BYTES;
+    const uint32_t lane_off = (uint32_t)lane * BS;
+    const uint32_t zslot = (uint32_t)D.trash;
+    auto fetch = [&](const uint32_t *tab, int t) -> C {
+        uint32_t sl = uniform_u32(tab[t]);
+        sl = (sl & NEWFLAG) ? zslot : sl;
+        const char *blk = (const char *)D.pool + (uint64_t)sl * (BLK * BS);
+        if constexpr (ST == VL_F64)
+            return *(const double *)(blk + lane_off);
+        else if constexpr (ST == VL_F32)
+            return *(const float *)(blk + lane_off);
+        else
+            return bf16_to_f32(*(const uint16_t *)(blk + lane_off));
+    };
+    C a1 = 0, a2 = 0, a3 = 0, da_prev = 0, face_prev = 0;
+    double Fc_prev = 0.0, Ff_prev = 0.0;
+    const int G = (L + 7) / 8;
+    if (G == 1) build_next();
+    for (int g = 0; g < G; g++) {
+        const bool lastg = (g == G - 1);
+        const uint32_t *src = lastg ? Y : X;
+        const int fb = lastg ? 0 : 8 * (g + 1);
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int t = 8 * g + u;
+            const C a = q[u];
+            q[u] = fetch(src, fb + u);
+            const C dl = a1 - a2, dr = a - a1;
+            const C cen = (C)0.5 * (a - a2);
+            const C s2 = copysign((C)2.0, cen);
+            const C m = fmax((C)0, fmin(fmin(fabs(cen), s2 * dl), s2 * dr));
+            const C da = copysign(m, cen);
+            const C face = a2 + (C)0.5 * dl - (da - da_prev) * (C)(1.0 / 6.0);
+            const C ai = a2;
+            const C dL = ai - face_prev, dR = face - ai;
+            const C mL = fmax((C)0, fmin(fabs(dL), copysign((C)2.0, dL) * dR));
+            const C mR = fmax((C)0, fmin(fabs(dR), copysign((C)2.0, dR) * dL));
+            const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
+            const double Fc = fma(P, dRp, fma(Q, dLp, c * (double)ai));
+            const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
+            if (t >= 6 && t < L) {
+                const uint32_t sl3 = uniform_u32(X[t - 3]);
+                if (sl3 != ABSENT) {
+                    const uint32_t s3 = sl3 & ~NEWFLAG;
+                    char *dst = (char *)D.pool + (uint64_t)s3 * (BLK * BS);
+                    double nv;
+                    if constexpr (ST == VL_F64) {
+                        nv = (double)a3 + (Ff_prev - Ff);
+                        *(double *)(dst + lane_off) = nv;
+                    } else {
+                        const double x = (double)a3 + (Ff_prev - Ff) + carry;
+                        nv = Storage<ST>::round(x);
+                        carry = x - nv;
+                        if constexpr (ST == VL_F32)
+                            *(float *)(dst + lane_off) = (float)nv;
+                        else
+                            *(uint16_t *)(dst + lane_off) = Storage<VL_BF16>::encode(nv);
+                    }
+                    if constexpr (LAST) {
+                        const unsigned long long any = __ballot(nv >= smin);
+                        sflag[t - 3] = any ? 1 : 0;
+                    }
+                }
+            }
+            a3 = a2;
+            a2 = a1;
+            a1 = a;
+            da_prev = da;
+            face_prev = face;
+            Fc_prev = Fc;
+            Ff_prev = Ff;
+        }
+        if (g == 0 && G > 1) build_next();
+    }
+}
+
+template <int ST, bool LAST>
+__device__ __forceinline__ void sweep_stream(const Dev &D, const SweepParams &sp)
+{
+    using C = typename std::conditional<ST == VL_F64, double, float>::type;
+    __shared__ __align__(16) uint32_t s_tab[4][2][MAXL + 48];
+    __shared__ uint8_t s_flg[4][MAXL + 48];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int d = sp.d, L = sp.L, WL = sp.WL;
+    const int ld = (d == 0) ? (lane & 3) : (d == 1) ? ((lane >> 2) & 3) : (lane >> 4);
+    const int64_t nitems = min((int64_t)D.ctl->n_items, D.item_cap);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    double ledger_acc = 0.0;
+    int64_t it = (int64_t)blockIdx.x * 4 + wv;
+    if (it >= nitems) return;
+    uint32_t *X = s_tab[wv][0], *Y = s_tab[wv][1];
+    uint8_t *sflag = s_flg[wv];
+    build_slots(D, it, nitems, L, WL, lane, X);
+    wave_sync_lds();
+    const uint32_t zslot = (uint32_t)D.trash;
+    constexpr int BS = Storage<ST>::BYTES;
+    C q[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        uint32_t sl = uniform_u32(X[u]);
+        sl = (sl & NEWFLAG) ? zslot : sl;
+        const char *blk = (const char *)D.pool + (uint64_t)sl * (BLK * BS) + (uint32_t)lane * BS;
+        if constexpr (ST == VL_F64)
+            q[u] = *(const double *)blk;
+        else if constexpr (ST == VL_F32)
+            q[u] = *(const float *)blk;
+        else
+            q[u] = bf16_to_f32(*(const uint16_t *)blk);
+    }
+    for (; it < nitems; it += nwaves) {
+        const int64_t nit = it + nwaves;
+        const int32_t id = D.items[it].id;
+        const int bd = block_coord(D, d, id);
+        const double c = courant(D, d, 4 * bd + ld, sp.dt);
+        const unsigned long long npos = __ballot(c > 0.0), nneg = __ballot(c < 0.0);
+        double carry = 0.0;
+        auto build = [&]() {
+            build_slots(D, nit, nitems, L, WL, lane, Y);
+            wave_sync_lds();
+        };
+        if (npos == ~0ull)
+            march_stream<ST, 1, LAST>(D, X, Y, sflag, L, c, lane, sp.sparse_min, carry, q, build);
+        else if (nneg == ~0ull)
+            march_stream<ST, -1, LAST>(D, X, Y, sflag, L, c, lane, sp.sparse_min, carry, q, build);
+        else
+            march_stream<ST, 0, LAST>(D, X, Y, sflag, L, c, lane, sp.sparse_min, carry, q, build);
+        if constexpr (LAST) {
+            wave_sync_lds();
+            for (int t = 3 + lane; t < L - 3; t += 64) {
+                const uint32_t raw = X[t];
+                const uint32_t sl = raw & ~NEWFLAG;
+                if (raw != ABSENT && sl < (uint32_t)D.lcap) D.flags[sl] = sflag[t];
+            }
+        }
+        if constexpr (ST != VL_F64) {
+            const int p = D.items[it].pencil;
+            const int t1 = sp.lo1 + p % sp.n1, t2 = sp.lo2 + p / sp.n1;
+            const bool local = t1 >= H && t1 < H + D.n[sp.e1] && t2 >= H && t2 < H + D.n[sp.e2];
+            if (local) ledger_acc += carry;
+        }
+        wave_sync_lds();
+        uint32_t *tmp = X;
+        X = Y;
+        Y = tmp;
+    }
+    if constexpr (ST != VL_F64) {
+        double sum = ledger_acc;
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+        if (lane == 0 && sum != 0.0) atomicAdd(sp.ledger, sum);
+    }
+}
+
 template <int ST, bool LAST, int V>
 __global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
 {
-    sweep_body<ST, LAST, V>(D, sp);
+    if constexpr (VARIANTS[V].style == 2)
+        sweep_stream<ST, LAST>(D, sp);
+    else
+        sweep_body<ST, LAST, V>(D, sp);
 }
 
 template <int ST, bool LAST, int V, int MINW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW))) void k_sweep_occ(Dev D, SweepParams sp)
 {
-    sweep_body<ST, LAST, V>(D, sp);
+    if constexpr (VARIANTS[V].style == 2)
+        sweep_stream<ST, LAST>(D, sp);
+    else
+        sweep_body<ST, LAST, V>(D, sp);
 }
 
 template <typename K>
@@ -454,6 +666,8 @@ static void launch_st(const Dev &D, const SweepParams &sp, int v, hipStream_t st
     case 5: launch_variant<ST, LAST, 5>(D, sp, st); break;
     case 6: launch_variant<ST, LAST, 6>(D, sp, st); break;
     case 7: launch_variant<ST, LAST, 7>(D, sp, st); break;
+    case 8: launch_variant<ST, LAST, 8>(D, sp, st); break;
+    case 9: launch_variant<ST, LAST, 9>(D, sp, st); break;
     default: launch_variant<ST, LAST, 0>(D, sp, st); break;
     }
 }
