@@ -143,6 +143,19 @@ int vl_fill_ghosts(vl_partition *p);
  * VL_ERR_STALE_GHOSTS, VL_ERR_CAPACITY (with stats), VL_ERR_STATE, VL_ERR_HIP. */
 int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *stats);
 
+/* nsteps whole steps, each recorded once into a HIP graph and replayed: in
+ * VL_COALESCED mode the coalesced ghost update followed by the three shears
+ * and pruning (Section 3.2: one ghost update, then the translations in
+ * order); in VL_PER_SWEEP mode the per-direction refreshes and shears.  Each
+ * step gives the same state bit for bit as vl_fill_ghosts (coalesced mode)
+ * plus vl_translate_step.  The graphs are cached per starting list region
+ * and re-recorded when dt, mode, shear variant or Courant override change;
+ * recording uses a private stream, replays go to the partition's stream.
+ * Asynchronous: device-side errors surface at the next synchronising call.
+ * The ghost domain is stale afterwards.  nsteps >= 0.
+ * Errors: VL_ERR_ARG, VL_ERR_CFL, VL_ERR_STATE, VL_ERR_HIP. */
+int vl_graph_step(vl_partition *p, double dt, int32_t mode, int32_t nsteps);
+
 /* Velocity moments of the local cells, FP64 (paper silent; textbook
  * definitions): n = dv^3 sum f; V = dv^3 sum f v / n;
  * P_ab = m_p dv^3 sum f (v_a - V_a)(v_b - V_b), m_p = 1.67262192e-27 kg.

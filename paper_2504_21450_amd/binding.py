@@ -22,7 +22,8 @@ VL_OK, VL_ERR_ARG, VL_ERR_CFL, VL_ERR_CAPACITY, VL_ERR_STALE_GHOSTS, VL_ERR_HIP,
 EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_fill_ghosts", "vl_translate_step",
             "vl_moments", "vl_local_block_count", "vl_export_state", "vl_export_cells",
             "vl_set_courant_override", "vl_counters", "vl_profile_start", "vl_profile_stop",
-            "vl_autotune", "vl_set_variant", "vl_sync", "vl_destroy", "vl_status_string")
+            "vl_autotune", "vl_set_variant", "vl_graph_step", "vl_sync", "vl_destroy",
+            "vl_status_string")
 
 
 class VlDesc(C.Structure):
@@ -89,6 +90,8 @@ def load():
     L.vl_autotune.argtypes = [vp, dbl, i32, i32, vp, vp, i32]
     L.vl_set_variant.restype = C.c_int
     L.vl_set_variant.argtypes = [vp, i32]
+    L.vl_graph_step.restype = C.c_int
+    L.vl_graph_step.argtypes = [vp, dbl, i32, i32]
     L.vl_sync.restype = C.c_int
     L.vl_sync.argtypes = [vp]
     L.vl_destroy.restype = None
@@ -219,6 +222,11 @@ class Partition:
 
     def step_rc(self, dt, mode=VL_COALESCED):
         return self.lib.vl_translate_step(self.h, float(dt), int(mode), None)
+
+    def graph_step(self, dt, mode=VL_COALESCED, nsteps=1):
+        """nsteps whole steps (ghost update included in coalesced mode) replayed
+        from recorded HIP graphs; asynchronous."""
+        _check("vl_graph_step", self.lib.vl_graph_step(self.h, float(dt), int(mode), int(nsteps)))
 
     def moments(self, total=True):
         t = self.torch

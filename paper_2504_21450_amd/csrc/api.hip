@@ -107,8 +107,20 @@ struct Prof {
     std::vector<int> cls;
 };
 
+// Executable graphs of one whole step (coalesced fill when the mode has one,
+// then the translation kernels), one per starting list region.  They hold
+// dt, the mode, the shear variant and the Courant table pointer as launch
+// arguments, so any change of these drops them.
+struct GraphCache {
+    hipStream_t cap = nullptr;  // private stream, used only to record captures
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    double dt = 0.0;
+    int mode = -1, variant = -1;
+};
+
 struct vl_partition {
     Prof prof;
+    GraphCache graph;
     vl_desc desc;
     Layout lay;
     Dev D;
@@ -198,6 +210,98 @@ void update_box(const vl_partition *p, int mode, int s, int lo[3], int hi[3])
             lo[e] = 0;
             hi[e] = p->D.P[e];
         }
+}
+
+// The kernels of one translation step (growth, work list and shear per axis,
+// then pruning into the other local list region), enqueued on st with no
+// host read-back, so that the sequence can also be captured into a graph.
+void enqueue_translate(vl_partition *p, double dt, int mode, double *ledger, hipStream_t st)
+{
+    const Dev &D = p->D;
+    const int nxt = 1 - p->cur;
+    launch_book(D, BOOK_STEP_RESET, st);
+    for (int s = 0; s < 3; s++) {
+        const int d = p->desc.order[s];
+        int lo[3], hi[3];
+        update_box(p, mode, s, lo, hi);
+        if (mode == VL_PER_SWEEP) {
+            int flo[3], fhi[3];
+            for (int e = 0; e < 3; e++) {
+                flo[e] = H;
+                fhi[e] = H + D.n[e];
+            }
+            flo[d] = 0;
+            fhi[d] = D.P[d];
+            launch_book(D, BOOK_GHOST_RESET, st);
+            ProfScope ps(p, K_FILL);
+            launch_fill(D, flo, fhi, st);
+        }
+        launch_book(D, BOOK_SWEEP_RESET, st);
+        {
+            ProfScope ps(p, K_PLAN);
+            launch_plan(D, d, s, lo, hi, dt, p->cur, st);
+        }
+        {
+            ProfScope ps(p, K_SHEAR0 + s);
+            launch_sweep(D, d, s, lo, hi, dt, s == 2, ledger, st);
+        }
+    }
+    launch_book(D, nxt == 0 ? BOOK_PRUNE_RESET_A : BOOK_PRUNE_RESET_B, st);
+    {
+        ProfScope ps(p, K_PRUNE);
+        launch_prune(D, nxt, st);
+    }
+}
+
+
+void enqueue_fill(vl_partition *p, hipStream_t st)
+{
+    const Dev &D = p->D;
+    int lo[3] = {0, 0, 0}, hi[3] = {D.P[0], D.P[1], D.P[2]};
+    launch_book(D, BOOK_GHOST_RESET, st);
+    ProfScope ps(p, K_FILL);
+    launch_fill(D, lo, hi, st);
+}
+
+void drop_graphs(vl_partition *p)
+{
+    GraphCache &g = p->graph;
+    for (auto &e : g.exec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+    g.mode = g.variant = -1;
+}
+
+// Record the step that starts from list region p->cur into g.exec[p->cur].
+int capture_step(vl_partition *p, double dt, int mode)
+{
+    GraphCache &g = p->graph;
+    if (!g.cap) VL_HIP(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
+    const bool prof = p->prof.on;
+    p->prof.on = false;  // no event records inside the graph
+    VL_HIP(hipStreamBeginCapture(g.cap, hipStreamCaptureModeRelaxed));
+    if (mode == VL_COALESCED) enqueue_fill(p, g.cap);
+    enqueue_translate(p, dt, mode, p->D.red + 4, g.cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t le = hipGetLastError();
+    const hipError_t ee = hipStreamEndCapture(g.cap, &graph);
+    p->prof.on = prof;
+    if (le != hipSuccess || ee != hipSuccess || !graph) {
+        fprintf(stderr, "libvlasov: step capture failed: %s / %s\n", hipGetErrorString(le), hipGetErrorString(ee));
+        if (graph) (void)hipGraphDestroy(graph);
+        return VL_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        fprintf(stderr, "libvlasov: graph instantiation failed: %s\n", hipGetErrorString(ie));
+        return VL_ERR_HIP;
+    }
+    g.exec[p->cur] = exec;
+    return VL_OK;
 }
 
 }  // namespace
@@ -407,13 +511,7 @@ int vl_fill_ghosts(vl_partition *p)
 {
     if (!p) return VL_ERR_ARG;
     if (p->bad) return VL_ERR_STATE;
-    const Dev &D = p->D;
-    int lo[3] = {0, 0, 0}, hi[3] = {D.P[0], D.P[1], D.P[2]};
-    launch_book(D, BOOK_GHOST_RESET, p->stream);
-    {
-        ProfScope ps(p, K_FILL);
-        launch_fill(D, lo, hi, p->stream);
-    }
+    enqueue_fill(p, p->stream);
     VL_HIP(hipGetLastError());
     p->ghosts_valid = true;
     return VL_OK;
@@ -434,39 +532,8 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
         launch_reduce(D, D.cell_red, D.nlocal, D.red + 0, st);
         VL_HIP(hipMemsetAsync(D.red + 3, 0, sizeof(double), st));  // ledger of this step
     }
-    launch_book(D, BOOK_STEP_RESET, st);
-    for (int s = 0; s < 3; s++) {
-        const int d = p->desc.order[s];
-        int lo[3], hi[3];
-        update_box(p, mode, s, lo, hi);
-        if (mode == VL_PER_SWEEP) {
-            int flo[3], fhi[3];
-            for (int e = 0; e < 3; e++) {
-                flo[e] = H;
-                fhi[e] = H + D.n[e];
-            }
-            flo[d] = 0;
-            fhi[d] = D.P[d];
-            launch_book(D, BOOK_GHOST_RESET, st);
-            ProfScope ps(p, K_FILL);
-            launch_fill(D, flo, fhi, st);
-        }
-        launch_book(D, BOOK_SWEEP_RESET, st);
-        {
-            ProfScope ps(p, K_PLAN);
-            launch_plan(D, d, s, lo, hi, dt, p->cur, st);
-        }
-        {
-            ProfScope ps(p, K_SHEAR0 + s);
-            launch_sweep(D, d, s, lo, hi, dt, s == 2, stats ? D.red + 3 : D.red + 4, st);
-        }
-    }
+    enqueue_translate(p, dt, mode, stats ? D.red + 3 : D.red + 4, st);
     const int nxt = 1 - p->cur;
-    launch_book(D, nxt == 0 ? BOOK_PRUNE_RESET_A : BOOK_PRUNE_RESET_B, st);
-    {
-        ProfScope ps(p, K_PRUNE);
-        launch_prune(D, nxt, st);
-    }
     VL_HIP(hipGetLastError());
     p->cur = nxt;
     p->ghosts_valid = false;
@@ -502,6 +569,35 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
             p->bad = true;
             return VL_ERR_CAPACITY;
         }
+    }
+    return VL_OK;
+}
+
+int vl_graph_step(vl_partition *p, double dt, int32_t mode, int32_t nsteps)
+{
+    if (!p || nsteps < 0) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    if (mode != VL_COALESCED && mode != VL_PER_SWEEP) return VL_ERR_ARG;
+    if (!(dt > 0.0) || !isfinite(dt)) return VL_ERR_ARG;
+    if (check_cfl(p, dt)) return VL_ERR_CFL;
+    GraphCache &g = p->graph;
+    if (g.dt != dt || g.mode != mode || g.variant != p->D.sweep_variant) {
+        drop_graphs(p);
+        g.dt = dt;
+        g.mode = mode;
+        g.variant = p->D.sweep_variant;
+    }
+    for (int k = 0; k < nsteps; k++) {
+        if (!g.exec[p->cur]) {
+            int rc = capture_step(p, dt, mode);
+            if (rc) {
+                drop_graphs(p);
+                return rc;
+            }
+        }
+        VL_HIP(hipGraphLaunch(g.exec[p->cur], p->stream));
+        p->cur = 1 - p->cur;
+        p->ghosts_valid = false;
     }
     return VL_OK;
 }
@@ -584,6 +680,7 @@ int vl_set_variant(vl_partition *p, int32_t variant)
 {
     if (!p || variant < 0 || variant >= sweep_variants()) return VL_ERR_ARG;
     p->D.sweep_variant = variant;
+    drop_graphs(p);
     return VL_OK;
 }
 
@@ -764,6 +861,7 @@ int vl_set_courant_override(vl_partition *p, const double *table, int32_t stride
 {
     if (!p) return VL_ERR_ARG;
     if (p->bad) return VL_ERR_STATE;
+    drop_graphs(p);
     if (!table) {
         p->has_cover = false;
         p->D.cover = nullptr;
@@ -792,6 +890,8 @@ void vl_destroy(vl_partition *p)
 {
     if (!p) return;
     for (hipEvent_t e : p->prof.ev) (void)hipEventDestroy(e);
+    drop_graphs(p);
+    if (p->graph.cap) (void)hipStreamDestroy(p->graph.cap);
     delete p;
 }
 
