@@ -12,6 +12,10 @@ Prints one JSON line.  `value` is useful phase-space cell updates per second
 (3 x local phase-space cells per step, inputs resident in HBM), `roofline`
 describes the shear kernel (the dominant one) against the 8 TB/s HBM peak,
 and `cpu_baseline` the FP64 CPU oracle on a sub-box of the same workload.
+
+--workload mixture selects the uneven batched-cell workload instead: cold
+solar-wind cells (~80 blocks) beside hot mixture cells (~4,300 blocks) in a
+blob pattern (--hot sets the hot fraction), sampled on the device.
 """
 import argparse
 import hashlib
@@ -63,7 +67,12 @@ def cpu_baseline(w, sample, min_seconds=10.0, max_steps=6):
     size = tuple(int(v) for v in sample.split("x"))
     lo = tuple((w.n[d] - size[d]) // 2 for d in range(3))
     cells = W.subbox_cells(w.n, lo, size, 3)
-    off, ids, f = W.take_cells(w.offsets, w.ids, w.f, cells)
+    if w.f is not None:
+        off, ids, f = W.take_cells(w.offsets, w.ids, w.f, cells)
+    else:  # device-sampled workload: the host sampler gives the oracle its input
+        off, ids, f = W.sample_cells(W.table_model(w.fields["params"]), w.nblk, w.vmin, w.dv,
+                                     w.sparse_min, w.vbuffer, w.seed, cells,
+                                     threads=min(16, os.cpu_count() or 1), batch=4)
     o = oracle.OraclePartition(size, w.nblk, w.dx, w.vmin, w.dv, w.order, w.sparse_min, w.vbuffer)
     o.load_padded(off, ids, f)
     oracle.lib().vlo_mark_ghosts_valid(o._h)
@@ -98,12 +107,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--storage", default="f64", choices=sorted(STORAGES))
     ap.add_argument("--mode", default="coalesced", choices=["coalesced", "per_sweep"])
+    ap.add_argument("--workload", default="maxwellian", choices=["maxwellian", "mixture"])
+    ap.add_argument("--hot", type=float, default=0.4, help="hot-cell fraction of the mixture")
     ap.add_argument("--nx", default="64x64x32", help="local spatial box")
-    ap.add_argument("--cpu-sample", default="24x24x12")
+    ap.add_argument("--cpu-sample", default=None, help="oracle sub-box (default 24x24x12; "
+                                                         "8x8x4 for the mixture)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--slack", type=float, default=2.0,
-                    help="block and list capacity over the initial block count (the distribution
-                         spreads by ~0.7 %% of blocks per step)")
+    ap.add_argument("--slack", type=float, default=None,
+                    help="block and list capacity over the initial block count (default 2.0; 1.25 "
+                         "for the mixture; the smooth case spreads by ~0.7 %% of blocks per step)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the shear-kernel autotuner (it runs real steps before warmup)")
     ap.add_argument("--variant", type=int, default=None, help="fixed shear variant (with --no-autotune)")
@@ -128,15 +140,41 @@ def main():
     from paper_2504_21450_amd import workloads as W
 
     n = tuple(int(v) for v in args.nx.split("x"))
+    mixture = args.workload == "mixture"
+    slack = args.slack if args.slack is not None else (1.25 if mixture else 2.0)
+    cpu_sample = args.cpu_sample or ("8x8x4" if mixture else "24x24x12")
     t0 = time.time()
     log("generating workload %s ..." % (n,))
-    w = W.maxwellian_sparse(n=n, threads=min(16, os.cpu_count() or 1))
-    w.storage = STORAGES[args.storage]
+    tune = None
+    if mixture:
+        from paper_2504_21450_amd import devsample
+        if args.autotune:
+            # tune on a smaller partition of the same mixture, so that the
+            # measured partition starts its timed steps near its initial state
+            proxy_n = tuple(min(v, c) for v, c in zip(n, (32, 32, 16)))
+            wp = W.blob_mixture(n=proxy_n, hot_fraction=args.hot, sample=False,
+                                storage=STORAGES[args.storage])
+            pp = devsample.sample_partition(wp, slack=2.0)
+            best, ms = pp.autotune(wp.dt, B.VL_COALESCED if args.mode == "coalesced" else B.VL_PER_SWEEP,
+                                   steps_per_variant=2)
+            tune = {"variant": best, "shear_ms_per_step": ms, "proxy": "x".join(map(str, proxy_n))}
+            log("autotune on %s: variant %d, shear ms/step per variant %s"
+                % (tune["proxy"], best, ["%.2f" % v for v in ms]))
+            pp.close()
+            del pp
+            torch.cuda.empty_cache()
+        w = W.blob_mixture(n=n, hot_fraction=args.hot, sample=False, storage=STORAGES[args.storage])
+        p = devsample.sample_partition(w, slack=slack)
+        if tune is not None:
+            p.set_variant(tune["variant"])
+    else:
+        w = W.maxwellian_sparse(n=n, threads=min(16, os.cpu_count() or 1))
+        w.storage = STORAGES[args.storage]
+        p = B.Partition.from_workload(w, slack=slack)
     log("generated %d blocks (%.3e phase-space cells) in %.1f s"
         % (w.nblocks, w.nblocks * 64.0, time.time() - t0))
     mode = B.VL_COALESCED if args.mode == "coalesced" else B.VL_PER_SWEEP
 
-    p = B.Partition.from_workload(w, slack=args.slack)
     log("partition initialised: workspace %.1f GB" % (p.ws_bytes / 1e9))
     dn = torch.empty(p.ncell, dtype=torch.float64, device="cuda:0")
     dV = torch.empty(p.ncell * 3, dtype=torch.float64, device="cuda:0")
@@ -154,8 +192,7 @@ def main():
         if rc:
             raise B.VlasovError("vl_moments", rc)
 
-    tune = None
-    if args.autotune:
+    if args.autotune and not mixture:
         best, ms = p.autotune(w.dt, mode, steps_per_variant=2)
         tune = {"variant": best, "shear_ms_per_step": ms}
         log("autotune: variant %d, shear ms/step per variant %s" % (best, ["%.2f" % v for v in ms]))
@@ -209,6 +246,7 @@ def main():
                                % (w.name, args.storage, args.mode),
                    "cells": list(n), "velocity_cells": [4 * b for b in w.nblk],
                    "local_blocks": int(blocks1), "local_ps_cells": int(blocks1 * 64),
+                   "blocks_per_cell": [int(v) for v in np.percentile(np.diff(w.offsets), [0, 50, 100])],
                    "dt_over_dx_max_courant": w.max_courant()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -259,8 +297,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a %s sub-box ..." % args.cpu_sample)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        log("timing the CPU oracle on a %s sub-box ..." % cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(w, cpu_sample)
     print(json.dumps(out), flush=True)
 
 

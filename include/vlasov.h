@@ -118,12 +118,22 @@ size_t vl_workspace_bytes(const vl_desc *d);
  * dev_workspace: >= vl_workspace_bytes(d) bytes of device memory, 256-byte
  * aligned.  hip_stream: a hipStream_t (NULL = default stream).  Values are
  * converted to the storage type (round to nearest even).  The ghost domain
- * is invalid until vl_fill_ghosts.  Synchronises the stream.
+ * is invalid until vl_fill_ghosts.  f may be NULL: the values are then zero
+ * until vl_load_values supplies them.  Synchronises the stream.
  * Errors: VL_ERR_ARG (descriptor, alignment, size, unsorted or out-of-range
  * ids), VL_ERR_CAPACITY (more blocks than block_capacity), VL_ERR_HIP. */
 int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes,
                       void *hip_stream, const int64_t *cell_offsets,
                       const int32_t *block_ids, const double *f, vl_partition **out);
+
+/* Values of the initial blocks [first_block, first_block + nblocks) in the
+ * CSR order given to vl_init_partition (64 FP64 values per block, lane order,
+ * in device memory), converted to the storage type as there.  For states
+ * sampled on the device in pieces.  Only before the first translation step
+ * (else VL_ERR_STATE); marks the ghost domain stale.  Asynchronous: dev_f
+ * must stay valid until the stream has passed this call.
+ * Errors: VL_ERR_ARG (range or pointer), VL_ERR_STATE, VL_ERR_HIP. */
+int vl_load_values(vl_partition *p, int64_t first_block, int64_t nblocks, const double *dev_f);
 
 /* Coalesced ghost update (Section 3, Fig. 3a): every cell of the padded box
  * outside the local box receives the block list and values of its periodic

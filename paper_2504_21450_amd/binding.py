@@ -19,7 +19,7 @@ VL_COALESCED, VL_PER_SWEEP = 0, 1
 VL_OK, VL_ERR_ARG, VL_ERR_CFL, VL_ERR_CAPACITY, VL_ERR_STALE_GHOSTS, VL_ERR_HIP, VL_ERR_STATE = (
     0, -1, -2, -3, -4, -5, -6)
 
-EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_fill_ghosts", "vl_translate_step",
+EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_load_values", "vl_fill_ghosts", "vl_translate_step",
             "vl_moments", "vl_local_block_count", "vl_export_state", "vl_export_cells",
             "vl_set_courant_override", "vl_counters", "vl_profile_start", "vl_profile_stop",
             "vl_autotune", "vl_set_variant", "vl_graph_step", "vl_sync", "vl_destroy",
@@ -66,6 +66,8 @@ def load():
     L.vl_workspace_bytes.argtypes = [C.POINTER(VlDesc)]
     L.vl_init_partition.restype = C.c_int
     L.vl_init_partition.argtypes = [C.POINTER(VlDesc), vp, C.c_size_t, vp, vp, vp, vp, C.POINTER(vp)]
+    L.vl_load_values.restype = C.c_int
+    L.vl_load_values.argtypes = [vp, i64, i64, vp]
     L.vl_fill_ghosts.restype = C.c_int
     L.vl_fill_ghosts.argtypes = [vp]
     L.vl_translate_step.restype = C.c_int
@@ -154,7 +156,7 @@ class Partition:
         self.ncell = int(np.prod(self.n))
         offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         ids = np.ascontiguousarray(ids, dtype=np.int32)
-        f = np.ascontiguousarray(f, dtype=np.float64)
+        f = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
         nb = int(offsets[-1])
         NB = int(np.prod(nblk))
         nghost = int(np.prod([v + 6 for v in self.n])) - self.ncell
@@ -219,6 +221,12 @@ class Partition:
                 "pruned_mass": st.pruned_mass, "ledger_mass": st.ledger_mass,
                 "blocks": st.local_blocks, "updated_ps": tuple(st.updated_ps),
                 "read_ps": tuple(st.read_ps), "items": tuple(st.items)}
+
+    def load_values(self, first_block, nblocks, dev_f):
+        """Values of initial blocks [first_block, first_block + nblocks) from a
+        device FP64 tensor (before the first step; asynchronous)."""
+        _check("vl_load_values", self.lib.vl_load_values(self.h, int(first_block), int(nblocks),
+                                                         C.c_void_p(dev_f.data_ptr())))
 
     def step_rc(self, dt, mode=VL_COALESCED):
         return self.lib.vl_translate_step(self.h, float(dt), int(mode), None)

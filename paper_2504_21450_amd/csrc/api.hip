@@ -22,7 +22,7 @@ constexpr int RED_DOUBLES = 1024;
 inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t pool, ring, flags, lstart, lcount, lcapa, lid, lslot, rows, items, masks, ctl, cover, cellred,
+    size_t pool, ring, flags, lstart, lcount, lcapa, lsorted, lid, lslot, rows, items, masks, ctl, cover, cellred,
         red, cellcnt, total;
     int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap;
     int wlmax, cover_stride;
@@ -66,11 +66,11 @@ Layout make_layout(const vl_desc *d)
     L.nlocal = (int64_t)d->n[0] * d->n[1] * d->n[2];
     L.nghost = L.N - L.nlocal;
     const int64_t lcap = d->block_capacity, gcap = d->ghost_block_capacity;
-    L.LA = lcap + lcap / 4 + 32 * L.nlocal;
-    L.LG = gcap + gcap / 4 + 32 * L.nghost;
+    L.LA = lcap + lcap / 2 + 32 * L.nlocal;
+    L.LG = gcap + gcap / 2 + 32 * L.nghost;
     L.row_cap = lcap + gcap + 64;
     const int64_t tot = lcap + gcap;
-    L.item_cap = tot <= (1 << 24) ? tot + 64 : std::max<int64_t>(1 << 24, tot / 2);
+    L.item_cap = tot <= (1 << 24) ? tot + 64 : std::max<int64_t>(1 << 24, tot / 4);
     int maxP = std::max(P[0], std::max(P[1], P[2]));
     L.wlmax = (maxP + 31) / 32;
     int maxnv = 4 * std::max(d->nblk[0], std::max(d->nblk[1], d->nblk[2]));
@@ -83,6 +83,7 @@ Layout make_layout(const vl_desc *d)
     L.lstart = o;  o = align_up(o + (size_t)L.N * 8);
     L.lcount = o;  o = align_up(o + (size_t)L.N * 4);
     L.lcapa = o;   o = align_up(o + (size_t)L.N * 4);
+    L.lsorted = o; o = align_up(o + (size_t)L.N * 4);
     const size_t nl = (size_t)(2 * L.LA + L.LG);
     L.lid = o;     o = align_up(o + nl * 4);
     L.lslot = o;   o = align_up(o + nl * 4);
@@ -127,6 +128,8 @@ struct vl_partition {
     hipStream_t stream;
     char *ws;
     int cur;            // local list region in use (0 or 1)
+    int64_t init_blocks; // blocks given at init; their slots are 0 .. init_blocks - 1
+    bool loadable;      // no step yet: vl_load_values may still overwrite values
     bool ghosts_valid;
     bool bad;
     bool has_cover;
@@ -219,6 +222,7 @@ void enqueue_translate(vl_partition *p, double dt, int mode, double *ledger, hip
 {
     const Dev &D = p->D;
     const int nxt = 1 - p->cur;
+    p->loadable = false;
     launch_book(D, BOOK_STEP_RESET, st);
     for (int s = 0; s < 3; s++) {
         const int d = p->desc.order[s];
@@ -343,7 +347,7 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
     for (int64_t q = 0; q < L.nlocal; q++)
         if (cell_offsets[q + 1] < cell_offsets[q]) return VL_ERR_ARG;
     const int64_t total = cell_offsets[L.nlocal];
-    if (total > 0 && (!block_ids || !f)) return VL_ERR_ARG;
+    if (total > 0 && !block_ids) return VL_ERR_ARG;
     for (int64_t q = 0; q < L.nlocal; q++)
         for (int64_t k = cell_offsets[q]; k < cell_offsets[q + 1]; k++) {
             if (block_ids[k] < 0 || block_ids[k] >= NB) return VL_ERR_ARG;
@@ -357,6 +361,8 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
     p->stream = (hipStream_t)hip_stream;
     p->ws = (char *)dev_workspace;
     p->cur = 0;
+    p->init_blocks = total;
+    p->loadable = true;
     p->ghosts_valid = false;
     p->bad = false;
     p->has_cover = false;
@@ -391,6 +397,7 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
     D.lstart = (int64_t *)(w + L.lstart);
     D.lcount = (int32_t *)(w + L.lcount);
     D.lcapa = (int32_t *)(w + L.lcapa);
+    D.lsorted = (int32_t *)(w + L.lsorted);
     D.lid = (int32_t *)(w + L.lid);
     D.lslot = (int32_t *)(w + L.lslot);
     D.reg_off[0] = 0;
@@ -450,6 +457,7 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
         if (hipMemcpy(D.ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
         if (hipMemcpy(D.lstart, lstart.data(), L.N * 8, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
         if (hipMemcpy(D.lcount, lcount.data(), L.N * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        if (hipMemcpy(D.lsorted, lcount.data(), L.N * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
         if (hipMemcpy(D.lcapa, lcapa.data(), L.N * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
         if (!lid.empty()) {
             if (hipMemcpy(D.lid, lid.data(), lid.size() * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
@@ -462,7 +470,9 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
         // payload, converted to the storage type in chunks
         const int bs = storage_bytes(d->storage);
         const int64_t nval = total * BLK;
-        if (d->storage == VL_F64) {
+        if (!f) {  // values follow through vl_load_values
+            if (nval > 0 && hipMemset(D.pool, 0, (size_t)nval * bs) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        } else if (d->storage == VL_F64) {
             if (nval > 0 && hipMemcpy(D.pool, f, (size_t)nval * 8, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
         } else {
             const int64_t chunk = 1 << 24;
@@ -504,6 +514,19 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
         return rc;
     }
     *out = p;
+    return VL_OK;
+}
+
+int vl_load_values(vl_partition *p, int64_t first_block, int64_t nblocks, const double *dev_f)
+{
+    if (!p) return VL_ERR_ARG;
+    if (p->bad || !p->loadable) return VL_ERR_STATE;
+    if (first_block < 0 || nblocks < 0 || first_block > p->init_blocks - nblocks) return VL_ERR_ARG;
+    if (nblocks == 0) return VL_OK;
+    if (!dev_f) return VL_ERR_ARG;
+    launch_load(p->D, first_block, nblocks, dev_f, p->stream);
+    VL_HIP(hipGetLastError());
+    p->ghosts_valid = false;
     return VL_OK;
 }
 
@@ -765,7 +788,7 @@ int vl_export_cells(vl_partition *p, const int64_t *cells, int64_t ncells, int64
         cell_offsets[i + 1] = total;
     }
     if (total > cap_blocks) return VL_ERR_ARG;
-    if (total > 0 && (!block_ids || !f)) return VL_ERR_ARG;
+    if (total > 0 && !block_ids) return VL_ERR_ARG;
     std::vector<int32_t> slots((size_t)total);
     std::vector<std::pair<int32_t, int32_t>> ent;
     for (int64_t i = 0; i < ncells; i++) {
@@ -824,7 +847,7 @@ int vl_export_state(vl_partition *p, int64_t *cell_offsets, int32_t *block_ids, 
         cell_offsets[q + 1] = total;
     }
     if (total > cap_blocks) return VL_ERR_ARG;
-    if (total > 0 && (!block_ids || !f)) return VL_ERR_ARG;
+    if (total > 0 && !block_ids) return VL_ERR_ARG;
     std::vector<int32_t> slots((size_t)total);
     std::vector<std::pair<int32_t, int32_t>> ent;
     for (int64_t q = 0; q < D.nlocal; q++) {

@@ -71,17 +71,6 @@ __device__ inline long long block_sum_ll(long long v, long long *s_tmp)
     return r;
 }
 
-// index of the pencil cell holding flat entry q (s_pre: prefix of counts, L+1)
-__device__ inline int find_cell(const int *s_pre, int L, int q)
-{
-    int lo = 0, hi = L;  // s_pre[lo] <= q < s_pre[hi]
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (s_pre[mid] <= q) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -98,7 +87,9 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     int *s_cap = (int *)q; q += sizeof(int) * MAXL;
     int *s_new = (int *)q; q += sizeof(int) * MAXL;
     int *s_req = (int *)q; q += sizeof(int) * MAXL;   // new blocks of this chunk per cell
-    int *s_pre = (int *)q; q += sizeof(int) * (MAXL + 4);
+    int *s_pos = (int *)q; q += sizeof(int) * MAXL;   // first list entry of the current chunk
+    int *s_cc = (int *)q; q += sizeof(int) * MAXL;    // list entries in the current chunk
+    int *s_srt = (int *)q; q += sizeof(int) * MAXL;   // ascending prefix length of each list
     uint32_t *s_bm = (uint32_t *)q; q += sizeof(uint32_t) * W;
     int *s_rank = (int *)q; q += sizeof(int) * (W + 1);
     uint32_t *s_pres = (uint32_t *)q; q += sizeof(uint32_t) * R * WL;
@@ -127,35 +118,26 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         s_cap[i] = D.lcapa[c];
         s_new[i] = 0;
         s_req[i] = 0;
+        s_pos[i] = 0;
+        s_srt[i] = D.lsorted[c];
     }
     for (int w = tid; w < W; w += 256) s_bm[w] = 0u;
     __syncthreads();
-    if (tid == 0) {
-        int run = 0;
-        for (int i = 0; i < L; i++) {
-            s_pre[i] = run;
-            run += s_cnt[i];
-        }
-        s_pre[L] = run;
-    }
-    __syncthreads();
-    const int T = s_pre[L];
+    const int lane = tid & 63, wave = tid >> 6;
 
-    // 1. union bitmap (4 independent entries per thread in flight)
-    for (int q0 = tid; q0 < T; q0 += 1024) {
-        int32_t ids[4];
+    // 1. union bitmap: a wavefront reads one cell's sorted list at a time,
+    //    four coalesced loads per lane in flight
+    for (int i = wave; i < L; i += 4) {
+        const int cnt = s_cnt[i];
+        const int32_t *lst = D.lid + s_cs[i];
+        for (int e0 = lane; e0 < cnt; e0 += 256) {
+            int32_t ids[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const int qf = q0 + 256 * k;
-            ids[k] = -1;
-            if (qf < T) {
-                const int i = find_cell(s_pre, L, qf);
-                ids[k] = D.lid[s_cs[i] + (qf - s_pre[i])];
-            }
+            for (int k = 0; k < 4; k++) ids[k] = (e0 + 64 * k < cnt) ? lst[e0 + 64 * k] : -1;
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (ids[k] >= 0) atomicOr(&s_bm[ids[k] >> 5], 1u << (ids[k] & 31));
         }
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-            if (ids[k] >= 0) atomicOr(&s_bm[ids[k] >> 5], 1u << (ids[k] & 31));
     }
     __syncthreads();
     // 2. ranks
@@ -181,30 +163,42 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         const int rn = min(R, U - r0);
         for (int k = tid; k < rn * WL; k += 256) s_pres[k] = 0u;
         __syncthreads();
-        // presence masks of this chunk
-        for (int q0 = tid; q0 < T; q0 += 1024) {
-            int32_t ids[4];
-            int cells[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const int qf = q0 + 256 * k;
-                ids[k] = -1;
-                cells[k] = 0;
-                if (qf < T) {
-                    const int i = find_cell(s_pre, L, qf);
-                    cells[k] = i;
-                    ids[k] = D.lid[s_cs[i] + (qf - s_pre[i])];
+        // presence masks of this chunk.  Ranks grow along the ascending
+        // prefix of a list, so a cell's prefix entries in the chunk are the
+        // run that starts at s_pos[i] and ends at the first rank beyond the
+        // chunk; the entries appended by earlier shears of the step (the
+        // tail) are all looked at in every chunk.
+        for (int i = wave; i < L; i += 4) {
+            const int cnt = s_cnt[i], srt = s_srt[i];
+            const int32_t *lst = D.lid + s_cs[i];
+            const uint32_t cbit = 1u << (i & 31);
+            const int cw = i >> 5;
+            int pos = s_pos[i];
+            while (pos < srt) {
+                const int e = pos + lane;
+                int32_t id = -1;
+                int k = rn;
+                if (e < srt) {
+                    id = lst[e];
+                    const int w = id >> 5;
+                    k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
                 }
+                const bool in = k < rn;
+                if (in) {
+                    atomicOr(&s_pres[k * WL + cw], cbit);
+                    s_id[k] = id;
+                }
+                const int n_in = (int)__popcll(__ballot(in));
+                pos += n_in;
+                if (n_in < 64) break;
             }
-#pragma unroll
-            for (int kk = 0; kk < 4; kk++) {
-                const int32_t id = ids[kk];
-                if (id < 0) continue;
-                const int i = cells[kk];
+            if (lane == 0) s_cc[i] = pos - s_pos[i];
+            for (int e = srt + lane; e < cnt; e += 64) {
+                const int32_t id = lst[e];
                 const int w = id >> 5;
                 const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
                 if (k >= 0 && k < rn) {
-                    atomicOr(&s_pres[k * WL + (i >> 5)], 1u << (i & 31));
+                    atomicOr(&s_pres[k * WL + cw], cbit);
                     s_id[k] = id;
                 }
             }
@@ -379,42 +373,51 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                 }
             }
         }
-        // rows of the blocks already held
+        // rows of the blocks already held: the chunk's run of each list
+        // (its place may have moved, its entries have not)
         if (rows_ok) {
-            for (int q0 = tid; q0 < T; q0 += 1024) {
-                int32_t ids[4], sls[4];
-                int cells[4];
+            for (int i = wave; i < L; i += 4) {
+                const int64_t at0 = s_cs[i] + s_pos[i];
+                const int n = s_cc[i];
+                const int iw = i >> 5;
+                const uint32_t below = (1u << (i & 31)) - 1u;
+                for (int e0 = lane; e0 < n; e0 += 256) {
+                    int32_t ids[4], sls[4];
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const int qf = q0 + 256 * k;
-                    ids[k] = -1;
-                    cells[k] = 0;
-                    sls[k] = 0;
-                    if (qf < T) {
-                        const int i = find_cell(s_pre, L, qf);
-                        const int64_t at = s_cs[i] + (qf - s_pre[i]);
-                        cells[k] = i;
-                        ids[k] = D.lid[at];
-                        sls[k] = D.lslot[at];
+                    for (int k = 0; k < 4; k++) {
+                        const int e = e0 + 64 * k;
+                        ids[k] = (e < n) ? D.lid[at0 + e] : -1;
+                        sls[k] = (e < n) ? D.lslot[at0 + e] : 0;
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < 4; kk++) {
+                        const int32_t id = ids[kk];
+                        if (id < 0) continue;
+                        const int w = id >> 5;
+                        const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
+                        if (s_ai[k + 1] == s_ai[k]) continue;
+                        int pos = 0;
+                        for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
+                        pos += popc(s_pres[k * WL + iw] & below);
+                        D.rows[(int64_t)rb + s_ro[k] + pos] = sls[kk];
                     }
                 }
-#pragma unroll
-                for (int kk = 0; kk < 4; kk++) {
-                    const int32_t id = ids[kk];
-                    if (id < 0) continue;
-                    const int i = cells[kk];
+                // the tail
+                const int64_t cs = s_cs[i];
+                for (int e = s_srt[i] + lane; e < s_cnt[i]; e += 64) {
+                    const int32_t id = D.lid[cs + e];
                     const int w = id >> 5;
                     const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
-                    if (k < 0 || k >= rn) continue;
-                    if (s_ai[k + 1] == s_ai[k]) continue;
+                    if (k < 0 || k >= rn || s_ai[k + 1] == s_ai[k]) continue;
                     int pos = 0;
-                    const int iw = i >> 5;
                     for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
-                    pos += popc(s_pres[k * WL + iw] & ((1u << (i & 31)) - 1u));
-                    D.rows[(int64_t)rb + s_ro[k] + pos] = sls[kk];
+                    pos += popc(s_pres[k * WL + iw] & below);
+                    D.rows[(int64_t)rb + s_ro[k] + pos] = D.lslot[cs + e];
                 }
             }
         }
+        __syncthreads();
+        for (int i = tid; i < L; i += 256) s_pos[i] += s_cc[i];
         __syncthreads();
     }
 
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
 
 size_t plan_lds_bytes(int W, int R, int WL)
 {
-    size_t b = sizeof(int64_t) * MAXL + sizeof(int) * MAXL * 4 + sizeof(int) * (MAXL + 4);
+    size_t b = sizeof(int64_t) * MAXL + sizeof(int) * MAXL * 7;
     b += sizeof(uint32_t) * W + sizeof(int) * (W + 1);
     b += (size_t)R * WL * 4 * 2 + (size_t)R * 4 + (size_t)(R + 1) * 4 * 3;
     return b + 64;
@@ -461,8 +464,9 @@ void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3]
     pp.ulo = lo[d];
     pp.uhi = hi[d];
     pp.dt = dt;
-    // chunk size: keep the workgroup's LDS at <= 56 KiB
-    const size_t budget = 56 * 1024;
+    // chunk size: keep the workgroup's LDS at <= 34 KiB (plus ~3 KiB static),
+    // so four planner workgroups fit a compute unit's 160 KiB
+    const size_t budget = 34 * 1024;
     size_t fixed = plan_lds_bytes(D.W, 0, pp.WL);
     size_t per = (size_t)pp.WL * 8 + 16;
     int R = (fixed < budget) ? (int)((budget - fixed) / per) : 64;

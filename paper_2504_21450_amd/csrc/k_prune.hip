@@ -244,6 +244,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
         D.lstart[c] = ns;
         D.lcount[c] = nkeep;
         D.lcapa[c] = cap;
+        D.lsorted[c] = nkeep;
     }
 }
 

@@ -1,6 +1,8 @@
 // Block-store kernels: allocator book-keeping, the ghost update (periodic
 // image copy of block lists and payloads), per-cell mass, deterministic
 // reductions and the FP64 velocity moments.
+#include <algorithm>
+
 #include "vl_internal.h"
 #include "vl_storage.h"
 
@@ -58,6 +60,28 @@ void launch_iota_ring(const Dev &D, int64_t first, int64_t count, hipStream_t st
     hipLaunchKernelGGL(k_iota_ring, dim3((unsigned)g), dim3(256), 0, st, D, first, count);
 }
 
+// values of blocks [first, first + n) given in FP64, converted to the storage
+// type (slot k holds block k of the initial CSR order)
+template <int ST>
+__global__ __launch_bounds__(256) void k_load(Dev D, int64_t first, int64_t nval, const double *f)
+{
+    using S = Storage<ST>;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nval; i += stride)
+        S::store(D.pool, first * BLK + i, f[i]);
+}
+
+void launch_load(const Dev &D, int64_t first, int64_t n, const double *f, hipStream_t st)
+{
+    const int64_t nval = n * BLK;
+    const unsigned g = (unsigned)std::min<int64_t>((nval + 255) / 256, 1 << 20);
+    switch (D.storage) {
+    case VL_F64: hipLaunchKernelGGL(k_load<VL_F64>, dim3(g), dim3(256), 0, st, D, first, nval, f); break;
+    case VL_F32: hipLaunchKernelGGL(k_load<VL_F32>, dim3(g), dim3(256), 0, st, D, first, nval, f); break;
+    default: hipLaunchKernelGGL(k_load<VL_BF16>, dim3(g), dim3(256), 0, st, D, first, nval, f); break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // ghost update: every non-local cell of the box [lo, lo + ext) receives the
 // list and payload of its periodic image.  One wavefront per cell.
@@ -102,6 +126,7 @@ __global__ __launch_bounds__(256) void k_fill(Dev D, int lo0, int lo1, int lo2, 
             D.lstart[c] = D.reg_off[2];
             D.lcount[c] = 0;
             D.lcapa[c] = 0;
+            D.lsorted[c] = 0;
         }
         return;
     }
@@ -111,6 +136,7 @@ __global__ __launch_bounds__(256) void k_fill(Dev D, int lo0, int lo1, int lo2, 
         D.lstart[c] = ls;
         D.lcount[c] = cnt;
         D.lcapa[c] = cap;
+        D.lsorted[c] = D.lsorted[s];
     }
     for (int e = lane; e < cnt; e += 64) {
         D.lid[ls + e] = D.lid[ss + e];

@@ -76,6 +76,7 @@ struct Dev {
     uint8_t *flags;          // content flag per local slot (set by the last shear)
     int64_t *lstart;
     int32_t *lcount, *lcapa;
+    int32_t *lsorted;        // length of the ascending prefix of each list (growth appends after it)
     int32_t *lid, *lslot;
     int64_t reg_off[3], reg_cap[3];
     int32_t *rows;
@@ -136,6 +137,7 @@ __device__ inline int block_dirs(const Dev &D, int d, int32_t b, double dt)
 // ---- launches (defined in the kernel sources, called by the host API) ----
 void launch_book(const Dev &D, int op, hipStream_t st);
 void launch_iota_ring(const Dev &D, int64_t first_free, int64_t count, hipStream_t st);
+void launch_load(const Dev &D, int64_t first, int64_t n, const double *f, hipStream_t st);
 void launch_fill(const Dev &D, const int lo[3], const int hi[3], hipStream_t st);
 void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, int cur,
                  hipStream_t st);

@@ -196,8 +196,9 @@ def _component_radius2(comp, thresh):
     <= 2 components stays below thresh); -1 where the peak is too low."""
     spa = (K_B / M_P) * comp["Tpar"]
     spe = (K_B / M_P) * comp["Tperp"]
-    peak = comp["n"] / ((2.0 * np.pi) ** 1.5 * spe * np.sqrt(spa))
-    r = 1.01 * peak / (0.5 * thresh)
+    with np.errstate(divide="ignore", invalid="ignore"):   # absent components
+        peak = comp["n"] / ((2.0 * np.pi) ** 1.5 * spe * np.sqrt(spa))
+        r = 1.01 * peak / (0.5 * thresh)
     out = np.full(r.shape, -1.0)
     ok = r > 1.0
     out[ok] = 2.0 * np.maximum(spa, spe)[ok] * np.log(r[ok])
@@ -357,6 +358,105 @@ def maxwellian_sparse(seed=21452, n=(64, 64, 32), cells=None, threads=None, step
     w = Workload(name, tuple(n), dx, nblk, vmin, dv, dt, steps, 1e-15, 6, storage, (0, 1, 2),
                  offsets, ids, f, seed)
     w.fields = {"n": dens, "T": temp, "V": vel}
+    return w
+
+
+# --------------------------------------------------------------------------
+# uneven batched cells: cold solar wind and hot magnetosheath-like mixtures
+# --------------------------------------------------------------------------
+# per-cell component table: (ncell, 2, 10) float64 rows
+#   [n, Vx, Vy, Vz, Tpar, Tperp, bx, by, bz, 0]; n = 0 marks an absent component
+NCOMP, NPAR = 2, 10
+BHAT = np.array([1.0, 1.0, 1.0]) / math.sqrt(3.0)   # parallel direction (Section 4.1's B)
+
+
+def blob_field(rng, n, nblobs=16, rmin=3.0, rmax=8.0):
+    """Sum of `nblobs` periodic Gaussians exp(-|x - c|^2 / (2 r^2)) over the
+    cell centres of an n-box (minimum-image distances, in cells), centres
+    uniform in the box and radii uniform in [rmin, rmax]; flat x-fastest."""
+    c = rng.uniform(0.0, 1.0, size=(nblobs, 3)) * np.asarray(n, dtype=np.float64)
+    r = rng.uniform(rmin, rmax, size=nblobs)
+    x = [np.arange(n[d]) + 0.5 for d in range(3)]
+    out = np.zeros((n[2], n[1], n[0]))
+    for k in range(nblobs):
+        d2 = []
+        for d in range(3):
+            t = np.abs(x[d] - c[k, d])
+            t = np.minimum(t, n[d] - t)
+            d2.append(t * t)
+        out += np.exp(-(d2[2][:, None, None] + d2[1][None, :, None] + d2[0][None, None, :])
+                      / (2.0 * r[k] * r[k]))
+    return out.reshape(-1)
+
+
+def mixture_params(seed, n, hot_fraction):
+    """Component table of the blob mixture.  Cells whose blob field lies in the
+    top `hot_fraction` are hot: a bi-Maxwellian core (0.9 n_h, T_par = 5e6 K,
+    T_perp = 1e7 K, V = 0) plus a beam (0.1 n_h, 800 km/s along bhat,
+    T = 1e6 K), n_h = 1e6 m^-3; the others are cold solar wind (1e6 m^-3,
+    T = 1e5 K, V = (-750, 0, 0) km/s, Section 2.2)."""
+    rng = np.random.default_rng(seed)
+    B = blob_field(rng, n)
+    ncell = B.size
+    hot = np.zeros(ncell, dtype=bool)
+    nh = int(round(hot_fraction * ncell))
+    if nh > 0:
+        hot[np.argsort(-B, kind="stable")[:nh]] = True
+    P = np.zeros((ncell, NCOMP, NPAR))
+    cold = ~hot
+    P[cold, 0, 0] = 1e6
+    P[cold, 0, 1:4] = (-750e3, 0.0, 0.0)
+    P[cold, 0, 4:6] = 1e5
+    P[cold, 0, 6:9] = (1.0, 0.0, 0.0)
+    P[hot, 0, 0] = 0.9e6
+    P[hot, 0, 4] = 5e6
+    P[hot, 0, 5] = 1e7
+    P[hot, 0, 6:9] = BHAT
+    P[hot, 1, 0] = 0.1e6
+    P[hot, 1, 1:4] = 800e3 * BHAT
+    P[hot, 1, 4:6] = 1e6
+    P[hot, 1, 6:9] = BHAT
+    return P, hot
+
+
+def table_model(P):
+    """A sample_cells model reading the component table P."""
+    def model(c):
+        comps = []
+        for k in range(P.shape[1]):
+            q = P[c, k]
+            comps.append({"n": q[:, 0], "V": q[:, 1:4], "Tpar": q[:, 4], "Tperp": q[:, 5],
+                          "bhat": q[:, 6:9]})
+        return comps
+    return model
+
+
+def blob_mixture(seed=21454, n=(96, 96, 48), hot_fraction=0.4, cells=None, threads=None,
+                 steps=20, storage=VL_F32, sample=True):
+    """Uneven batched cells: the blob mixture on an n-box with the velocity mesh
+    of the sparse Maxwellian case (100^3 cells, dv = 30 km/s, +-1500 km/s),
+    blocks kept where max f >= 1e-15 s^3 m^-6 plus the 6 face neighbours
+    (about 80 blocks per cold cell, about 4000 per hot one).  The hot cells
+    are the top `hot_fraction` of a field of 16 periodic Gaussian blobs of
+    radius 3..8 cells (0.4: the uneven case; about 0.1: a mean near 500
+    blocks).  With sample=False only the component table is built (for
+    device-side sampling); `cells` restricts host sampling to a subset."""
+    dx = (300e3,) * 3
+    nblk = (25, 25, 25)
+    dv = (30e3,) * 3
+    vmin = (-1500e3,) * 3
+    P, hot = mixture_params(seed, n, hot_fraction)
+    offsets = ids = f = None
+    if sample:
+        if cells is None:
+            cells = np.arange(n[0] * n[1] * n[2])
+        offsets, ids, f = sample_cells(table_model(P), nblk, vmin, dv, 1e-15, 6, seed, cells,
+                                       threads=threads, batch=16)
+    dt = 0.5 * dx[0] / 1485e3
+    name = "blob-mixture-%dx%dx%d-hot%g-v100" % (tuple(n) + (hot_fraction,))
+    w = Workload(name, tuple(n), dx, nblk, vmin, dv, dt, steps, 1e-15, 6, storage, (0, 1, 2),
+                 offsets, ids, f, seed)
+    w.fields = {"params": P, "hot": hot}
     return w
 
 
