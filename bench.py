@@ -44,16 +44,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage):
-    """HBM bytes per shear launch from the committed rocprofv3 counter runs,
-    if they were taken on the current kernel source; else None."""
+def measured_traffic(storage, variant, workload):
+    """HBM bytes per shear launch from the committed rocprofv3 counter runs of
+    the same command, if they were taken on the current kernel source with the
+    same shear variant; else None."""
     path = os.path.join(ROOT, "profiles", "shear_traffic_%s.json" % storage)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("workload") != workload:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("hbm_bytes_per_launch", {}).get(str(variant))
 
 
 def cpu_baseline(w, sample, min_seconds=10.0, max_steps=6):
@@ -118,7 +119,9 @@ def main():
                          "for the mixture; the smooth case spreads by ~0.7 %% of blocks per step)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the shear-kernel autotuner (it runs real steps before warmup)")
-    ap.add_argument("--variant", type=int, default=None, help="fixed shear variant (with --no-autotune)")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="shear variant for the timed steps (the autotuner's steps still run unless "
+                         "--no-autotune, so the state evolves as in a default run)")
     ap.add_argument("--graph-steps", type=int, default=None,
                     help="steps replayed from recorded HIP graphs after the timed region "
                          "(default: --steps; 0 to skip)")
@@ -196,8 +199,12 @@ def main():
         best, ms = p.autotune(w.dt, mode, steps_per_variant=2)
         tune = {"variant": best, "shear_ms_per_step": ms}
         log("autotune: variant %d, shear ms/step per variant %s" % (best, ["%.2f" % v for v in ms]))
-    elif args.variant is not None:
+    variant = tune["variant"] if tune else 0
+    if args.variant is not None:
         p.set_variant(args.variant)
+        variant = args.variant
+        if tune:
+            tune["overridden_by"] = args.variant
     for _ in range(args.warmup):
         step()
     p.sync()
@@ -227,7 +234,7 @@ def main():
     per_launch = shear_bytes / max(shear_n, 1)
     avg_launch_s = shear_ms / max(shear_n, 1) / 1e3
     achieved = per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(args.storage)
+    traffic = measured_traffic(args.storage, variant, w.name)
 
     out = {
         "metric": METRIC,
@@ -250,7 +257,7 @@ def main():
                    "dt_over_dx_max_courant": w.max_courant()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sweep (PPM shear)",
+                     "kernel": "k_sweep (PPM shear), variant %d" % variant,
                      "algorithmic_bytes_per_launch": per_launch,
                      "avg_launch_ms": 1e3 * avg_launch_s, "launches": shear_n},
         "computed_updates_per_s": computed / elapsed,
