@@ -68,6 +68,8 @@ def lib():
         L.vlo_fill_ghosts.argtypes = [C.c_void_p]
         L.vlo_mark_ghosts_valid.argtypes = [C.c_void_p]
         L.vlo_update_box.argtypes = [C.c_void_p, C.c_int32, C.c_int32, i32p, i32p]
+        L.vlo_set_gt_level.restype = C.c_int32
+        L.vlo_set_gt_level.argtypes = [C.c_void_p, C.c_int32]
         L.vlo_step.restype = C.c_int
         L.vlo_step.argtypes = [C.c_void_p, C.c_double, C.c_int32, f64p]
         L.vlo_local_mass.restype = C.c_double
@@ -110,9 +112,11 @@ class OraclePartition:
                                    float(sparse_min), int(vbuffer))
 
     @classmethod
-    def from_workload(cls, w, order=None):
+    def from_workload(cls, w, order=None, gt_level=3):
         p = cls(w.n, w.nblk, w.dx, w.vmin, w.dv, order or w.order, w.sparse_min, w.vbuffer)
         p.load_local(w.offsets, w.ids, w.f)
+        if gt_level != 3:
+            p.set_gt_level(gt_level)
         return p
 
     def __del__(self):
@@ -181,6 +185,12 @@ class OraclePartition:
     # -- the method ----------------------------------------------------------
     def fill_ghosts(self):
         lib().vlo_fill_ghosts(self._h)
+
+    def set_gt_level(self, k):
+        """Ghost Translation level of the coalesced mode (Section 3.2): the
+        later shears' ghost layers computed by each shear, 1..3."""
+        if lib().vlo_set_gt_level(self._h, int(k)) != 0:
+            raise ValueError("gt level must be 1, 2 or 3")
 
     def update_box(self, mode, s):
         lo = np.zeros(3, np.int32)

@@ -87,13 +87,13 @@ def source_ratio_closed(n, k):
     return (source_union_closed(n, k) - n ** 3) / (3 * 2 * (STENCIL + 1) * n * n)
 
 
-def pull_update_boxes(n, order=(0, 1, 2)):
-    """Update boxes of the flux (pull) form, derived from the GT3 lattice sets:
+def pull_update_boxes(n, order=(0, 1, 2), k=3):
+    """Update boxes of the flux (pull) form, derived from the GTk lattice sets:
     in flux form a cell is recomputed by the shear along d exactly when it is
     d-active and not merely a face neighbour written to by the push form, i.e.
     the d-active set shrunk by one layer along d.  Returned as (lo, hi) per
     sweep, in coordinates relative to the local box origin."""
-    local, active, _ = gt_sets(n, 3, order)
+    local, active, _ = gt_sets(n, k, order)
     margin = (local.shape[0] - n) // 2
     out = []
     for d in order:

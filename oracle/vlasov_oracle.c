@@ -76,6 +76,7 @@ typedef struct {
     double sparse_min;
     int32_t vbuffer;
     int32_t ghosts_valid;
+    int32_t gt_level;  /* Ghost Translation level k = 1, 2, 3 (Section 3.2) */
     vlo_cell *cells;   /* padded box, x fastest */
     double *cover[3];  /* optional Courant table override per axis (nv[d]) */
 } vlo_part;
@@ -249,6 +250,7 @@ void *vlo_create(const int32_t *n, const int32_t *nblk, const double *dx, const 
     p->NB = nblk[0] * nblk[1] * nblk[2];
     p->sparse_min = sparse_min;
     p->vbuffer = vbuffer;
+    p->gt_level = VLO_H;
     p->cells = (vlo_cell *)calloc((size_t)p->P[0] * p->P[1] * p->P[2], sizeof(vlo_cell));
     return p;
 }
@@ -536,9 +538,11 @@ static void sweep(vlo_part *p, int d, const int lo[3], const int hi[3], double d
 }
 
 /* Update box of shear s (0, 1, 2 in sweep order) in padded coordinates.
- * Coalesced (GT3): shear s also covers the ghost layers of the axes swept
- * after it, since those cells feed the later stencils (Section 3.1).
- * Classical: the local box. */
+ * Coalesced: shear s also covers the ghost layers of the axes swept after it,
+ * since those cells feed the later stencils (Section 3.1); Ghost Translation
+ * of level k computes only the k layers nearest the local domain and leaves
+ * the others at their ghost-update values (Section 3.2: GT3 all three, GT1
+ * one).  Classical: the local box. */
 void vlo_update_box(void *h, int32_t mode, int32_t s, int32_t *lo, int32_t *hi)
 {
     vlo_part *p = (vlo_part *)h;
@@ -549,9 +553,19 @@ void vlo_update_box(void *h, int32_t mode, int32_t s, int32_t *lo, int32_t *hi)
     if (mode == VLO_COALESCED)
         for (int t = s + 1; t < 3; t++) {
             int e = p->order[t];
-            lo[e] = 0;
-            hi[e] = p->P[e];
+            lo[e] = VLO_H - p->gt_level;
+            hi[e] = VLO_H + p->n[e] + p->gt_level;
         }
+}
+
+/* Ghost Translation level of the coalesced mode: 1, 2 or 3 (default 3).
+ * Returns 0, or -1 for another value. */
+int32_t vlo_set_gt_level(void *h, int32_t k)
+{
+    vlo_part *p = (vlo_part *)h;
+    if (k < 1 || k > VLO_H) return -1;
+    p->gt_level = k;
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
