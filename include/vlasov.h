@@ -72,7 +72,10 @@ typedef struct vl_desc {
                              the paper's Z->X->Y = {2,0,1} */
     int32_t storage;      /* VL_F64, VL_F32 or VL_BF16 */
     int32_t stencil;      /* PPM stencil half-width; must be 2 (Section 2.1) */
-    int32_t gt_level;     /* ghost-translation level; must be 3 (exact GT3, Section 3.2) */
+    int32_t gt_level;     /* Ghost Translation level k of VL_COALESCED steps (Section 3.2):
+                             shear s recomputes the k ghost layers nearest the local box
+                             along the axes swept after it; 3 (GT3) is exact, 1 (GT1) and
+                             2 (GT2) leave the outer layers at their ghost-update values */
     int32_t vbuffer;      /* velocity-space buffer kept around content blocks:
                              0, 6 (face neighbours) or 26 (all neighbours) */
     int32_t reserved0;    /* must be 0 */

@@ -147,7 +147,7 @@ class Partition:
 
     def __init__(self, n, nblk, dx, vmin, dv, offsets, ids, f, storage=VL_F64, order=(0, 1, 2),
                  sparse_min=0.0, vbuffer=0, block_capacity=None, ghost_block_capacity=None,
-                 device="cuda:0", slack=2.5):
+                 device="cuda:0", slack=2.5, gt_level=3):
         import torch
 
         self.torch = torch
@@ -171,7 +171,7 @@ class Partition:
             if nghost * NB <= 20_000_000:
                 ghost_block_capacity = max(ghost_block_capacity, nghost * NB + 1024)
         self.desc = make_desc(n, nblk, dx, vmin, dv, order, storage, sparse_min, vbuffer,
-                              block_capacity, ghost_block_capacity)
+                              block_capacity, ghost_block_capacity, gt_level=gt_level)
         self.ws_bytes = workspace_bytes(self.desc)
         if self.ws_bytes == 0:
             raise VlasovError("vl_workspace_bytes", VL_ERR_ARG)

@@ -47,7 +47,7 @@ bool desc_ok(const vl_desc *d)
     }
     if (seen != 7) return false;
     if (d->storage != VL_F64 && d->storage != VL_F32 && d->storage != VL_BF16) return false;
-    if (d->stencil != 2 || d->gt_level != 3) return false;
+    if (d->stencil != 2 || d->gt_level < 1 || d->gt_level > H) return false;
     if (d->vbuffer != 0 && d->vbuffer != 6 && d->vbuffer != 26) return false;
     if (d->reserved0 != 0) return false;
     if (!isfinite(d->sparse_min)) return false;
@@ -207,11 +207,11 @@ void update_box(const vl_partition *p, int mode, int s, int lo[3], int hi[3])
         lo[e] = H;
         hi[e] = H + p->desc.n[e];
     }
-    if (mode == VL_COALESCED)
+    if (mode == VL_COALESCED)  // the later axes' ghost layers within the GT level
         for (int t = s + 1; t < 3; t++) {
             int e = p->desc.order[t];
-            lo[e] = 0;
-            hi[e] = p->D.P[e];
+            lo[e] = H - p->desc.gt_level;
+            hi[e] = H + p->desc.n[e] + p->desc.gt_level;
         }
 }
 

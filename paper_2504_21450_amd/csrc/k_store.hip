@@ -142,22 +142,24 @@ __global__ __launch_bounds__(256) void k_fill(Dev D, int lo0, int lo1, int lo2, 
         D.lid[ls + e] = D.lid[ss + e];
         D.lslot[ls + e] = (int32_t)(gslot0 + e);
     }
+    // source slots are read 64 at a time (one per lane) and broadcast from
+    // the lanes; 8 block copies in flight
     SW *pool = (SW *)D.pool;
-    int e = 0;
-    if (lane < WPB) {
-        for (; e + 4 <= cnt; e += 4) {
-            int64_t s0 = D.lslot[ss + e], s1 = D.lslot[ss + e + 1];
-            int64_t s2 = D.lslot[ss + e + 2], s3 = D.lslot[ss + e + 3];
-            SW v0 = pool[s0 * WPB + lane], v1 = pool[s1 * WPB + lane];
-            SW v2 = pool[s2 * WPB + lane], v3 = pool[s3 * WPB + lane];
-            pool[(gslot0 + e) * WPB + lane] = v0;
-            pool[(gslot0 + e + 1) * WPB + lane] = v1;
-            pool[(gslot0 + e + 2) * WPB + lane] = v2;
-            pool[(gslot0 + e + 3) * WPB + lane] = v3;
-        }
-        for (; e < cnt; e++) {
-            int64_t s0 = D.lslot[ss + e];
-            pool[(gslot0 + e) * WPB + lane] = pool[s0 * WPB + lane];
+    for (int g = 0; g < cnt; g += 64) {
+        const int ng = min(64, cnt - g);
+        const int32_t mys = lane < ng ? D.lslot[ss + g + lane] : 0;
+        if (lane < WPB) {
+            int k = 0;
+            for (; k + 8 <= ng; k += 8) {
+                SW v[8];
+#pragma unroll
+                for (int j = 0; j < 8; j++)
+                    v[j] = pool[(int64_t)__builtin_amdgcn_readlane(mys, k + j) * WPB + lane];
+#pragma unroll
+                for (int j = 0; j < 8; j++) pool[(gslot0 + g + k + j) * WPB + lane] = v[j];
+            }
+            for (; k < ng; k++)
+                pool[(gslot0 + g + k) * WPB + lane] = pool[(int64_t)__builtin_amdgcn_readlane(mys, k) * WPB + lane];
         }
     }
 }
@@ -322,20 +324,30 @@ __global__ __launch_bounds__(256) void k_moments(Dev D, double *dn, double *dV, 
         sxz += fx * uz;
         syz += fy * uz;
     };
-    // 8 blocks in flight per wavefront
-    int e = 0;
-    for (; e + 8 <= cnt; e += 8) {
-        int32_t b[8];
-        double f[8];
+    // ids and slots are read 64 at a time (one per lane) and broadcast from
+    // the lanes, so a block load waits on no other load; 8 blocks in flight
+    for (int g = 0; g < cnt; g += 64) {
+        const int ng = min(64, cnt - g);
+        const int32_t myid = lane < ng ? D.lid[ls + g + lane] : 0;
+        const int32_t myslot = lane < ng ? D.lslot[ls + g + lane] : 0;
+        int k = 0;
+        for (; k + 8 <= ng; k += 8) {
+            int32_t b[8];
+            double f[8];
 #pragma unroll
-        for (int k = 0; k < 8; k++) {
-            b[k] = D.lid[ls + e + k];
-            f[k] = Storage<ST>::load(D.pool, (int64_t)D.lslot[ls + e + k] * BLK + lane);
+            for (int j = 0; j < 8; j++) {
+                const int32_t sl = __builtin_amdgcn_readlane(myslot, k + j);
+                b[j] = __builtin_amdgcn_readlane(myid, k + j);
+                f[j] = Storage<ST>::load(D.pool, (int64_t)sl * BLK + lane);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; j++) acc(f[j], b[j]);
         }
-#pragma unroll
-        for (int k = 0; k < 8; k++) acc(f[k], b[k]);
+        for (; k < ng; k++) {
+            const int32_t sl = __builtin_amdgcn_readlane(myslot, k);
+            acc(Storage<ST>::load(D.pool, (int64_t)sl * BLK + lane), __builtin_amdgcn_readlane(myid, k));
+        }
     }
-    for (; e < cnt; e++) acc(Storage<ST>::load(D.pool, (int64_t)D.lslot[ls + e] * BLK + lane), D.lid[ls + e]);
     s0 = wave_sum(s0);
     s1x = wave_sum(s1x);
     s1y = wave_sum(s1y);

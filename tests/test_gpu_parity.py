@@ -200,3 +200,21 @@ def test_all_shear_variants_and_autotuner_are_bit_identical(sparse_small):
     b = gpu_partition(w)
     run_gpu(b, w.dt, nvar)
     assert all(np.array_equal(x, y) for x, y in zip(a.export(), b.export()))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_limited_ghost_translation_levels_match_oracle(sparse_small, k):
+    """GT1 / GT2 (Section 3.2): the device leaves the same ghost layers at
+    their ghost-update values as the oracle; values within 1e-12, lists exact."""
+    w = sparse_small
+    print_case("GT%d vs oracle" % k)
+    p = gpu_partition(w, gt_level=k)
+    gs = run_gpu(p, w.dt, 2, stats=True)
+    o = OraclePartition.from_workload(w, gt_level=k)
+    os_ = []
+    for _ in range(2):
+        o.fill_ghosts()
+        os_.append(o.step(w.dt))
+    compare_states(p.export(), o.export_local(), TOL64)
+    for g, r in zip(gs, os_):
+        assert g["updated_ps"] == r["updates"]

@@ -70,11 +70,13 @@ def good_desc(**kw):
 def test_workspace_bytes_and_descriptor_validation():
     assert B.workspace_bytes(good_desc()) > 0
     bad = [dict(n=(0, 3, 5)), dict(n=(251, 3, 5)), dict(nblk=(0, 2, 2)), dict(order=(0, 0, 1)),
-           dict(storage=3), dict(stencil=3), dict(gt_level=1), dict(vbuffer=7),
+           dict(storage=3), dict(stencil=3), dict(gt_level=0), dict(gt_level=4), dict(vbuffer=7),
            dict(dx=(0.0, 1.0, 1.0)), dict(dv=(1.0, -1.0, 1.0)), dict(block_capacity=0),
            dict(nblk=(64, 64, 64))]
     for kw in bad:
         assert B.workspace_bytes(good_desc(**kw)) == 0, kw
+    for k in (1, 2, 3):  # Ghost Translation levels
+        assert B.workspace_bytes(good_desc(gt_level=k)) > 0
     # larger pools need more workspace
     assert B.workspace_bytes(good_desc(block_capacity=5000)) > B.workspace_bytes(good_desc())
 
