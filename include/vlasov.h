@@ -143,6 +143,18 @@ int vl_load_values(vl_partition *p, int64_t first_block, int64_t nblocks, const 
  * image.  Once per step, before a VL_COALESCED step.  Asynchronous. */
 int vl_fill_ghosts(vl_partition *p);
 
+/* Coalesced ghost update from neighbouring partitions (Section 3, Fig. 3a:
+ * the one exchange of a Ghost Translation step): every ghost cell of p
+ * receives the block list and values of the cell at the same position in the
+ * partition that owns it.  nbr[(dx+1) + 3(dy+1) + 9(dz+1)] is the partition
+ * displaced by (dx, dy, dz) local boxes, nbr[13] == p; all 27 have the same
+ * local box (each side >= 3 cells), velocity mesh and storage, and live on the
+ * same device (or are readable from it).  The neighbours' local cells are read
+ * on p's stream: the caller orders their previous steps before this call and
+ * this call before their next steps.  Asynchronous.
+ * Errors: VL_ERR_ARG (mismatch, NULL, nbr[13] != p), VL_ERR_STATE, VL_ERR_HIP. */
+int vl_fill_ghosts_from(vl_partition *p, vl_partition *const *nbr);
+
 /* One translation step: three shears in desc.order (Section 2.1), each a PPM
  * remap of every velocity cell along its spatial pencils with Courant number
  * v dt / dx[d], followed by block pruning of the local cells.

@@ -19,7 +19,7 @@ VL_COALESCED, VL_PER_SWEEP = 0, 1
 VL_OK, VL_ERR_ARG, VL_ERR_CFL, VL_ERR_CAPACITY, VL_ERR_STALE_GHOSTS, VL_ERR_HIP, VL_ERR_STATE = (
     0, -1, -2, -3, -4, -5, -6)
 
-EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_load_values", "vl_fill_ghosts", "vl_translate_step",
+EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_load_values", "vl_fill_ghosts", "vl_fill_ghosts_from", "vl_translate_step",
             "vl_moments", "vl_local_block_count", "vl_export_state", "vl_export_cells",
             "vl_set_courant_override", "vl_counters", "vl_profile_start", "vl_profile_stop",
             "vl_autotune", "vl_set_variant", "vl_graph_step", "vl_sync", "vl_destroy",
@@ -69,6 +69,8 @@ def load():
     L.vl_load_values.restype = C.c_int
     L.vl_load_values.argtypes = [vp, i64, i64, vp]
     L.vl_fill_ghosts.restype = C.c_int
+    L.vl_fill_ghosts_from.restype = C.c_int
+    L.vl_fill_ghosts_from.argtypes = [vp, vp]
     L.vl_fill_ghosts.argtypes = [vp]
     L.vl_translate_step.restype = C.c_int
     L.vl_translate_step.argtypes = [vp, dbl, i32, C.POINTER(VlStepStats)]
@@ -221,6 +223,12 @@ class Partition:
                 "pruned_mass": st.pruned_mass, "ledger_mass": st.ledger_mass,
                 "blocks": st.local_blocks, "updated_ps": tuple(st.updated_ps),
                 "read_ps": tuple(st.read_ps), "items": tuple(st.items)}
+
+    def fill_ghosts_from(self, nbr):
+        """Ghost update from the 27 partitions around this one (nbr[13] is
+        self), indexed (dx+1) + 3(dy+1) + 9(dz+1); asynchronous."""
+        arr = (C.c_void_p * 27)(*[q.h.value if hasattr(q.h, "value") else q.h for q in nbr])
+        _check("vl_fill_ghosts_from", self.lib.vl_fill_ghosts_from(self.h, arr))
 
     def load_values(self, first_block, nblocks, dev_f):
         """Values of initial blocks [first_block, first_block + nblocks) from a

@@ -540,6 +540,36 @@ int vl_fill_ghosts(vl_partition *p)
     return VL_OK;
 }
 
+int vl_fill_ghosts_from(vl_partition *p, vl_partition *const *nbr)
+{
+    if (!p || !nbr || nbr[13] != p) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    const vl_desc &a = p->desc;
+    SrcTable src;
+    memset(&src, 0, sizeof(src));
+    src.remote = 1;
+    for (int q = 0; q < 27; q++) {
+        const vl_partition *o = nbr[q];
+        if (!o) return VL_ERR_ARG;
+        if (o->bad) return VL_ERR_STATE;
+        const vl_desc &b = o->desc;
+        for (int d = 0; d < 3; d++)
+            if (b.n[d] != a.n[d] || a.n[d] < H || b.nblk[d] != a.nblk[d] || b.vmin[d] != a.vmin[d] ||
+                b.dv[d] != a.dv[d])
+                return VL_ERR_ARG;
+        if (b.storage != a.storage) return VL_ERR_ARG;
+        src.part[q] = self_source(o->D);
+    }
+    launch_book(p->D, BOOK_GHOST_RESET, p->stream);
+    {
+        ProfScope ps(p, K_FILL);
+        launch_fill_from(p->D, src, p->stream);
+    }
+    VL_HIP(hipGetLastError());
+    p->ghosts_valid = true;
+    return VL_OK;
+}
+
 int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *stats)
 {
     if (!p) return VL_ERR_ARG;

@@ -94,7 +94,7 @@ __device__ inline int wrap_coord(int g, int n)
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_fill(Dev D, int lo0, int lo1, int lo2, int e0, int e1, int e2)
+__global__ __launch_bounds__(256) void k_fill(Dev D, SrcTable src, int lo0, int lo1, int lo2, int e0, int e1, int e2)
 {
     using SW = typename Storage<ST>::Word;
     constexpr int WPB = Storage<ST>::WORDS_PER_BLOCK;  // words per block (<= 64)
@@ -107,9 +107,28 @@ __global__ __launch_bounds__(256) void k_fill(Dev D, int lo0, int lo1, int lo2, 
     const int z = lo2 + (int)(w / ((int64_t)e0 * e1));
     if (is_local(D, x, y, z)) return;
     const int64_t c = cell_index(D, x, y, z);
-    const int64_t s = cell_index(D, wrap_coord(x, D.n[0]), wrap_coord(y, D.n[1]), wrap_coord(z, D.n[2]));
-    const int cnt = D.lcount[s];
-    const int64_t ss = D.lstart[s];
+    // source cell: the periodic image in this partition, or the cell of the
+    // neighbouring partition that holds this position (all local boxes equal,
+    // each at least 3 cells wide, so the neighbour is one box away)
+    int64_t s;
+    SrcPart sp;
+    if (!src.remote) {
+        s = cell_index(D, wrap_coord(x, D.n[0]), wrap_coord(y, D.n[1]), wrap_coord(z, D.n[2]));
+        sp = src.part[13];
+    } else {
+        const int g[3] = {x - H, y - H, z - H};
+        int l[3], q = 0, m = 1;
+        for (int d = 0; d < 3; d++) {
+            const int dir = g[d] < 0 ? -1 : (g[d] >= D.n[d] ? 1 : 0);
+            l[d] = g[d] - dir * D.n[d] + H;
+            q += (dir + 1) * m;
+            m *= 3;
+        }
+        s = cell_index(D, l[0], l[1], l[2]);
+        sp = src.part[q];
+    }
+    const int cnt = sp.lcount[s];
+    const int64_t ss = sp.lstart[s];
     const int cap = cnt + cnt / 4 + 32;
     unsigned long long lb = 0, sb = 0;
     if (lane == 0) {
@@ -136,45 +155,79 @@ __global__ __launch_bounds__(256) void k_fill(Dev D, int lo0, int lo1, int lo2, 
         D.lstart[c] = ls;
         D.lcount[c] = cnt;
         D.lcapa[c] = cap;
-        D.lsorted[c] = D.lsorted[s];
+        D.lsorted[c] = sp.lsorted[s];
     }
     for (int e = lane; e < cnt; e += 64) {
-        D.lid[ls + e] = D.lid[ss + e];
+        D.lid[ls + e] = sp.lid[ss + e];
         D.lslot[ls + e] = (int32_t)(gslot0 + e);
     }
     // source slots are read 64 at a time (one per lane) and broadcast from
     // the lanes; 8 block copies in flight
     SW *pool = (SW *)D.pool;
+    const SW *spool = (const SW *)sp.pool;
     for (int g = 0; g < cnt; g += 64) {
         const int ng = min(64, cnt - g);
-        const int32_t mys = lane < ng ? D.lslot[ss + g + lane] : 0;
+        const int32_t mys = lane < ng ? sp.lslot[ss + g + lane] : 0;
         if (lane < WPB) {
             int k = 0;
             for (; k + 8 <= ng; k += 8) {
                 SW v[8];
 #pragma unroll
                 for (int j = 0; j < 8; j++)
-                    v[j] = pool[(int64_t)__builtin_amdgcn_readlane(mys, k + j) * WPB + lane];
+                    v[j] = spool[(int64_t)__builtin_amdgcn_readlane(mys, k + j) * WPB + lane];
 #pragma unroll
                 for (int j = 0; j < 8; j++) pool[(gslot0 + g + k + j) * WPB + lane] = v[j];
             }
             for (; k < ng; k++)
-                pool[(gslot0 + g + k) * WPB + lane] = pool[(int64_t)__builtin_amdgcn_readlane(mys, k) * WPB + lane];
+                pool[(gslot0 + g + k) * WPB + lane] = spool[(int64_t)__builtin_amdgcn_readlane(mys, k) * WPB + lane];
         }
     }
 }
 
+SrcPart self_source(const Dev &D)
+{
+    SrcPart p;
+    p.lstart = D.lstart;
+    p.lcount = D.lcount;
+    p.lsorted = D.lsorted;
+    p.lid = D.lid;
+    p.lslot = D.lslot;
+    p.pool = D.pool;
+    return p;
+}
+
+template <int ST>
+static void launch_fill_st(const Dev &D, const SrcTable &src, const int lo[3], const int hi[3], hipStream_t st)
+{
+    const int e0 = hi[0] - lo[0], e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
+    const int64_t waves = (int64_t)e0 * e1 * e2;
+    if (waves <= 0) return;
+    hipLaunchKernelGGL(k_fill<ST>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, D, src, lo[0], lo[1], lo[2],
+                       e0, e1, e2);
+}
+
+static void launch_fill_any(const Dev &D, const SrcTable &src, const int lo[3], const int hi[3], hipStream_t st)
+{
+    switch (D.storage) {
+    case VL_F64: launch_fill_st<VL_F64>(D, src, lo, hi, st); break;
+    case VL_F32: launch_fill_st<VL_F32>(D, src, lo, hi, st); break;
+    default: launch_fill_st<VL_BF16>(D, src, lo, hi, st); break;
+    }
+}
+
+void launch_fill_from(const Dev &D, const SrcTable &src, hipStream_t st)
+{
+    const int lo[3] = {0, 0, 0}, hi[3] = {D.P[0], D.P[1], D.P[2]};
+    launch_fill_any(D, src, lo, hi, st);
+}
+
 void launch_fill(const Dev &D, const int lo[3], const int hi[3], hipStream_t st)
 {
-    int e0 = hi[0] - lo[0], e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
-    int64_t waves = (int64_t)e0 * e1 * e2;
-    if (waves <= 0) return;
-    dim3 g((unsigned)((waves + 3) / 4));
-    switch (D.storage) {
-    case VL_F64: hipLaunchKernelGGL(k_fill<VL_F64>, g, dim3(256), 0, st, D, lo[0], lo[1], lo[2], e0, e1, e2); break;
-    case VL_F32: hipLaunchKernelGGL(k_fill<VL_F32>, g, dim3(256), 0, st, D, lo[0], lo[1], lo[2], e0, e1, e2); break;
-    default: hipLaunchKernelGGL(k_fill<VL_BF16>, g, dim3(256), 0, st, D, lo[0], lo[1], lo[2], e0, e1, e2); break;
-    }
+    SrcTable src;
+    memset(&src, 0, sizeof(src));
+    src.part[13] = self_source(D);
+    src.remote = 0;
+    launch_fill_any(D, src, lo, hi, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -138,7 +138,20 @@ __device__ inline int block_dirs(const Dev &D, int d, int32_t b, double dt)
 void launch_book(const Dev &D, int op, hipStream_t st);
 void launch_iota_ring(const Dev &D, int64_t first_free, int64_t count, hipStream_t st);
 void launch_load(const Dev &D, int64_t first, int64_t n, const double *f, hipStream_t st);
+// source of a ghost update: the partition itself (periodic images) or the 27
+// partitions around it (index (dx+1) + 3(dy+1) + 9(dz+1), same local box)
+struct SrcPart {
+    const int64_t *lstart;
+    const int32_t *lcount, *lsorted, *lid, *lslot;
+    const void *pool;
+};
+struct SrcTable {
+    SrcPart part[27];
+    int remote;  // 0: periodic images of the partition's own cells
+};
 void launch_fill(const Dev &D, const int lo[3], const int hi[3], hipStream_t st);
+void launch_fill_from(const Dev &D, const SrcTable &src, hipStream_t st);
+SrcPart self_source(const Dev &D);
 void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, int cur,
                  hipStream_t st);
 int sweep_variants();
