@@ -159,7 +159,7 @@ def main():
             proxy_n = tuple(min(v, c) for v, c in zip(n, (32, 32, 16)))
             wp = W.blob_mixture(n=proxy_n, hot_fraction=args.hot, sample=False,
                                 storage=STORAGES[args.storage])
-            pp = devsample.sample_partition(wp, slack=2.0)
+            pp = devsample.sample_partition(wp, slack=4.0)
             best, ms = pp.autotune(wp.dt, B.VL_COALESCED if args.mode == "coalesced" else B.VL_PER_SWEEP,
                                    steps_per_variant=2)
             tune = {"variant": best, "shear_ms_per_step": ms, "proxy": "x".join(map(str, proxy_n))}

@@ -178,12 +178,16 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
                 *(double *)(dst + lane_off) = nv;
             } else {
                 const double x = (double)a3 + (Ff_prev - Ff) + (live ? carry : 0.0);
-                nv = Storage<ST>::round(x);
+                if constexpr (ST == VL_F32) {
+                    const float q = (float)x;
+                    nv = (double)q;
+                    *(float *)(dst + lane_off) = q;
+                } else {
+                    const uint16_t h = bf16_rne_f64(x);
+                    nv = (double)bf16_to_f32(h);
+                    *(uint16_t *)(dst + lane_off) = h;
+                }
                 if (live) carry = x - nv;
-                if constexpr (ST == VL_F32)
-                    *(float *)(dst + lane_off) = (float)nv;
-                else
-                    *(uint16_t *)(dst + lane_off) = Storage<VL_BF16>::encode(nv);
             }
             if constexpr (LAST) {
                 const unsigned long long any = __ballot(nv >= smin);
@@ -272,12 +276,16 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
                         *(double *)(dst + lane_off) = nv;
                     } else {
                         const double x = (double)a3 + (Ff_prev - Ff) + carry;
-                        nv = Storage<ST>::round(x);
+                        if constexpr (ST == VL_F32) {
+                            const float q = (float)x;
+                            nv = (double)q;
+                            *(float *)(dst + lane_off) = q;
+                        } else {
+                            const uint16_t h = bf16_rne_f64(x);
+                            nv = (double)bf16_to_f32(h);
+                            *(uint16_t *)(dst + lane_off) = h;
+                        }
                         carry = x - nv;
-                        if constexpr (ST == VL_F32)
-                            *(float *)(dst + lane_off) = (float)nv;
-                        else
-                            *(uint16_t *)(dst + lane_off) = Storage<VL_BF16>::encode(nv);
                     }
                     if constexpr (LAST) {
                         const unsigned long long any = __ballot(nv >= smin);
@@ -505,12 +513,16 @@ __device__ __forceinline__ void march_stream(const Dev &D, const uint32_t *X, co
                         *(double *)(dst + lane_off) = nv;
                     } else {
                         const double x = (double)a3 + (Ff_prev - Ff) + carry;
-                        nv = Storage<ST>::round(x);
+                        if constexpr (ST == VL_F32) {
+                            const float q = (float)x;
+                            nv = (double)q;
+                            *(float *)(dst + lane_off) = q;
+                        } else {
+                            const uint16_t h = bf16_rne_f64(x);
+                            nv = (double)bf16_to_f32(h);
+                            *(uint16_t *)(dst + lane_off) = h;
+                        }
                         carry = x - nv;
-                        if constexpr (ST == VL_F32)
-                            *(float *)(dst + lane_off) = (float)nv;
-                        else
-                            *(uint16_t *)(dst + lane_off) = Storage<VL_BF16>::encode(nv);
                     }
                     if constexpr (LAST) {
                         const unsigned long long any = __ballot(nv >= smin);

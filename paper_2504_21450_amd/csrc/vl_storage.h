@@ -58,6 +58,22 @@ __host__ __device__ inline float bf16_to_f32(uint16_t h)
     return bits_f32(((uint32_t)h) << 16);
 }
 
+// FP64 -> BF16, round to nearest even, for finite values.  FP64 -> FP32 (to
+// nearest) can only change the BF16 rounding where it lands exactly on a BF16
+// midpoint (low half 0x8000) without being the value itself; there the FP32
+// word is moved one unit toward the value, so the midpoint no longer ties.
+__host__ __device__ inline uint16_t bf16_rne_f64(double d)
+{
+    const float t = (float)d;
+    uint32_t u = f32_bits(t);
+    const double back = (double)t;
+    const bool tie = (u & 0xFFFFu) == 0x8000u && back != d;
+    const uint32_t step = (fabs(d) > fabs(back)) ? 1u : 0xFFFFFFFFu;
+    u += tie ? step : 0u;
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 template <int ST>
 struct Storage;
 
@@ -96,7 +112,7 @@ struct Storage<VL_BF16> {
         return (double)bf16_to_f32(((const uint16_t *)pool)[i]);
     }
     __device__ static float loadf(const void *pool, int64_t i) { return bf16_to_f32(((const uint16_t *)pool)[i]); }
-    __device__ static uint16_t encode(double v) { return f32_to_bf16_rne(d2f_odd(v)); }
+    __device__ static uint16_t encode(double v) { return bf16_rne_f64(v); }
     __device__ static void store(void *pool, int64_t i, double v) { ((uint16_t *)pool)[i] = encode(v); }
     __device__ static double round(double v) { return (double)bf16_to_f32(encode(v)); }
 };
