@@ -378,28 +378,28 @@ __global__ __launch_bounds__(256) void k_moments(Dev D, double *dn, double *dV, 
         syz += fy * uz;
     };
     // ids and slots are read 64 at a time (one per lane) and broadcast from
-    // the lanes, so a block load waits on no other load; 8 blocks in flight
+    // the lanes, so a block load waits on no other load; the raw storage words
+    // of NF blocks are in flight (more for the narrower types, whose loads
+    // carry fewer bytes) and widened to FP64 only when summed
+    using T = typename Storage<ST>::T;
+    constexpr int NF = ST == VL_F64 ? 8 : 16;
+    const T *pool = (const T *)D.pool;
     for (int g = 0; g < cnt; g += 64) {
         const int ng = min(64, cnt - g);
         const int32_t myid = lane < ng ? D.lid[ls + g + lane] : 0;
         const int32_t myslot = lane < ng ? D.lslot[ls + g + lane] : 0;
         int k = 0;
-        for (; k + 8 <= ng; k += 8) {
-            int32_t b[8];
-            double f[8];
+        for (; k + NF <= ng; k += NF) {
+            T r[NF];
 #pragma unroll
-            for (int j = 0; j < 8; j++) {
-                const int32_t sl = __builtin_amdgcn_readlane(myslot, k + j);
-                b[j] = __builtin_amdgcn_readlane(myid, k + j);
-                f[j] = Storage<ST>::load(D.pool, (int64_t)sl * BLK + lane);
-            }
+            for (int j = 0; j < NF; j++)
+                r[j] = pool[(int64_t)__builtin_amdgcn_readlane(myslot, k + j) * BLK + lane];
 #pragma unroll
-            for (int j = 0; j < 8; j++) acc(f[j], b[j]);
+            for (int j = 0; j < NF; j++) acc(Storage<ST>::widen(r[j]), __builtin_amdgcn_readlane(myid, k + j));
         }
-        for (; k < ng; k++) {
-            const int32_t sl = __builtin_amdgcn_readlane(myslot, k);
-            acc(Storage<ST>::load(D.pool, (int64_t)sl * BLK + lane), __builtin_amdgcn_readlane(myid, k));
-        }
+        for (; k < ng; k++)
+            acc(Storage<ST>::widen(pool[(int64_t)__builtin_amdgcn_readlane(myslot, k) * BLK + lane]),
+                __builtin_amdgcn_readlane(myid, k));
     }
     s0 = wave_sum(s0);
     s1x = wave_sum(s1x);

@@ -86,6 +86,7 @@ struct Storage<VL_F64> {
     __device__ static double load(const void *pool, int64_t i) { return ((const double *)pool)[i]; }
     __device__ static void store(void *pool, int64_t i, double v) { ((double *)pool)[i] = v; }
     __device__ static double round(double v) { return v; }
+    __device__ static double widen(double v) { return v; }
 };
 
 template <>
@@ -99,6 +100,7 @@ struct Storage<VL_F32> {
     __device__ static void store(void *pool, int64_t i, double v) { ((float *)pool)[i] = (float)v; }
     // value actually stored for v (as FP64)
     __device__ static double round(double v) { return (double)(float)v; }
+    __device__ static double widen(float v) { return (double)v; }
 };
 
 template <>
@@ -115,6 +117,7 @@ struct Storage<VL_BF16> {
     __device__ static uint16_t encode(double v) { return bf16_rne_f64(v); }
     __device__ static void store(void *pool, int64_t i, double v) { ((uint16_t *)pool)[i] = encode(v); }
     __device__ static double round(double v) { return (double)bf16_to_f32(encode(v)); }
+    __device__ static double widen(uint16_t v) { return (double)bf16_to_f32(v); }
 };
 
 inline int storage_bytes(int st) { return st == VL_F64 ? 8 : st == VL_F32 ? 4 : 2; }
