@@ -57,7 +57,7 @@ def measured_traffic(storage, variant, workload):
     return d.get("hbm_bytes_per_launch", {}).get(str(variant))
 
 
-def cpu_baseline(w, sample, min_seconds=10.0, max_steps=6):
+def cpu_baseline(w, sample, min_seconds=10.0, max_steps=40):
     """Time the FP64 oracle on a sub-box of the workload (explicit ghost
     domain from the full box for the first step, then periodic)."""
     import numpy as np
