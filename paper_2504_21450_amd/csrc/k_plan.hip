@@ -173,24 +173,39 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
             const int32_t *lst = D.lid + s_cs[i];
             const uint32_t cbit = 1u << (i & 31);
             const int cw = i >> 5;
+            // 256 entries are loaded at once (the run usually continues) and
+            // taken 64 at a time until the first one beyond the chunk
             int pos = s_pos[i];
-            while (pos < srt) {
-                const int e = pos + lane;
-                int32_t id = -1;
-                int k = rn;
-                if (e < srt) {
-                    id = lst[e];
-                    const int w = id >> 5;
-                    k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
+            bool more = pos < srt;
+            while (more) {
+                int32_t ids[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int e = pos + 64 * u + lane;
+                    ids[u] = (e < srt) ? lst[e] : -1;
                 }
-                const bool in = k < rn;
-                if (in) {
-                    atomicOr(&s_pres[k * WL + cw], cbit);
-                    s_id[k] = id;
+                int taken = 0;
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    if (more) {
+                        const int32_t id = ids[u];
+                        int k = rn;
+                        if (id >= 0) {
+                            const int w = id >> 5;
+                            k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
+                        }
+                        const bool in = k < rn;
+                        if (in) {
+                            atomicOr(&s_pres[k * WL + cw], cbit);
+                            s_id[k] = id;
+                        }
+                        const int n_in = (int)__popcll(__ballot(in));
+                        taken += n_in;
+                        if (n_in < 64) more = false;
+                    }
                 }
-                const int n_in = (int)__popcll(__ballot(in));
-                pos += n_in;
-                if (n_in < 64) break;
+                pos += taken;
+                more = more && pos < srt;
             }
             if (lane == 0) s_cc[i] = pos - s_pos[i];
             for (int e = srt + lane; e < cnt; e += 64) {
