@@ -99,7 +99,7 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_a
 // there is nothing to write), which keeps the compiler's memory counters exact.
 template <int ST, int DIR, bool LAST>
 __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, uint8_t *sflag, int L, double c,
-                                          int lane, double smin, double &carry)
+                                          int lane, double smin, double &carry, int tb, int te)
 {
     using C = typename std::conditional<ST == VL_F64, double, float>::type;  // reconstruction type
     const bool pos = (DIR > 0) ? true : (DIR < 0) ? false : (c > 0.0);
@@ -139,11 +139,11 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
     C q[PF];
 #pragma unroll
     for (int u = 0; u < PF; u++) prv[u] = ABSENT;
-    slots8(0, cur);
+    const int t00 = tb & ~3;  // the slot table is read in aligned groups of 4
+    slots8(t00, cur);
 #pragma unroll
     for (int u = 0; u < PF; u++) q[u] = fetch(cur[u]);
-    const int Lr = (L + PF - 1) / PF * PF;
-    for (int t0 = 0; t0 < Lr; t0 += PF) {
+    for (int t0 = t00; t0 < te; t0 += PF) {
         slots8(t0 + PF, nxt);
 #pragma unroll
         for (int u = 0; u < PF; u++) {
@@ -215,7 +215,7 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
 // and outside the updated range; prefetch distance PFV cells.
 template <int ST, int DIR, bool LAST, int PFV>
 __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, uint8_t *sflag, int L, double c,
-                                           int lane, double smin, double &carry)
+                                           int lane, double smin, double &carry, int tb, int te)
 {
     using C = typename std::conditional<ST == VL_F64, double, float>::type;  // reconstruction type
     const bool pos = (DIR > 0) ? true : (DIR < 0) ? false : (c > 0.0);
@@ -244,9 +244,8 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
     double Fc_prev = 0.0, Ff_prev = 0.0;
     C q[PFV];
 #pragma unroll
-    for (int u = 0; u < PFV; u++) q[u] = fetch(u);
-    const int Lr = (L + PFV - 1) / PFV * PFV;
-    for (int t0 = 0; t0 < Lr; t0 += PFV) {
+    for (int u = 0; u < PFV; u++) q[u] = fetch(tb + u);
+    for (int t0 = tb; t0 < te; t0 += PFV) {
 #pragma unroll
         for (int u = 0; u < PFV; u++) {
             const int t = t0 + u;
@@ -318,13 +317,13 @@ constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 
 template <int ST, int DIR, bool LAST, int V>
 __device__ __forceinline__ void march(const Dev &D, const uint32_t *srow, uint8_t *sflag, int L, double c,
-                                      int lane, double smin, double &carry)
+                                      int lane, double smin, double &carry, int tb, int te)
 {
     constexpr VariantInfo vi = VARIANTS[V];
     if constexpr (vi.style == 1)
-        march_unc<ST, DIR, LAST>(D, srow, sflag, L, c, lane, smin, carry);
+        march_unc<ST, DIR, LAST>(D, srow, sflag, L, c, lane, smin, carry, tb, te);
     else
-        march_cond<ST, DIR, LAST, vi.pf>(D, srow, sflag, L, c, lane, smin, carry);
+        march_cond<ST, DIR, LAST, vi.pf>(D, srow, sflag, L, c, lane, smin, carry, tb, te);
 }
 
 template <int ST, bool LAST, int V>
@@ -340,10 +339,10 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     uint32_t *srow = s_slot[wv];
     double ledger_acc = 0.0;
-    const int Lr = (L + PF - 1) / PF * PF;
 
     for (int64_t it = (int64_t)blockIdx.x * 4 + wv; it < nitems; it += nwaves) {
         const Item item = D.items[it];
+        int tb = 0, te = 0;  // march range
         // per-cell slot table of this item in LDS: slot, slot|NEWFLAG or ABSENT
         {
             uint32_t m[MAXWL];
@@ -355,6 +354,20 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
                 pre[w + 1] = pre[w] + __popc(m[w]);
             }
             if (pre[MAXWL] == 0) continue;
+            // the march covers the cells from the first holding the block to
+            // three past the last (where the last one is written): before the
+            // first, every cell reads as zero and the reconstruction state is
+            // the zero state the march starts from
+            tb = -1;
+#pragma unroll
+            for (int w = 0; w < MAXWL; w++) {
+                if (m[w] != 0u) {
+                    if (tb < 0) tb = 32 * w + __builtin_ctz(m[w]);
+                    te = 32 * w + 31 - __builtin_clz(m[w]) + 4;
+                }
+            }
+            tb = __builtin_amdgcn_readfirstlane(tb);
+            te = __builtin_amdgcn_readfirstlane(te);
             const int half = lane >> 5, b = lane & 31;
 #pragma unroll
             for (int w = 0; w < MAXWL; w += 2) {
@@ -379,11 +392,11 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
         double carry = 0.0;
         uint8_t *sflag = s_flag[wv];
         if (npos == ~0ull)
-            march<ST, 1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry);
+            march<ST, 1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
         else if (nneg == ~0ull)
-            march<ST, -1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry);
+            march<ST, -1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
         else
-            march<ST, 0, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry);
+            march<ST, 0, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
         if constexpr (LAST) {
             // content flags of the written cells, one store per cell in parallel
             wave_sync_lds();
