@@ -169,7 +169,9 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
             // new value of cell t-3, stored unconditionally (to the sink when
             // there is nothing to store) so the memory counters stay exact
             const uint32_t raw3 = (u >= 3) ? cur[u - 3] : prv[u + PF - 3];
-            const bool live = (t >= 6) && (t < L) && (raw3 != ABSENT);
+            // the march runs in whole groups past te; cells from there on
+            // belong to the next segment and are written by its own march
+            const bool live = (t >= 6) && (t < L) && (t < te) && (raw3 != ABSENT);
             const uint32_t s3 = live ? (raw3 & ~NEWFLAG) : sink;
             char *dst = (char *)D.pool + (uint64_t)s3 * (BLK * BS);
             double nv;
@@ -191,7 +193,7 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
             }
             if constexpr (LAST) {
                 const unsigned long long any = __ballot(nv >= smin);
-                if (t >= 3) sflag[t - 3] = any ? 1 : 0;  // same value from every lane
+                if (t >= 3 && t < te) sflag[t - 3] = any ? 1 : 0;  // same value from every lane
             }
             a3 = a2;
             a2 = a1;
@@ -264,7 +266,7 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
             const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
             const double Fc = fma(P, dRp, fma(Q, dLp, c * (double)ai));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
-            if (t >= 6 && t < L) {
+            if (t >= 6 && t < L && t < te) {  // past te: the next segment's march
                 const uint32_t sl3 = uniform_u32(srow[t - 3]);
                 if (sl3 != ABSENT) {
                     const uint32_t s3 = sl3 & ~NEWFLAG;
@@ -326,6 +328,27 @@ __device__ __forceinline__ void march(const Dev &D, const uint32_t *srow, uint8_
         march_cond<ST, DIR, LAST, vi.pf>(D, srow, sflag, L, c, lane, smin, carry, tb, te);
 }
 
+// lowest set bit at position >= from of a MAXWL-word mask, or -1
+__device__ __forceinline__ int first_bit(const uint32_t (&v)[MAXWL], int from)
+{
+#pragma unroll
+    for (int w = 0; w < MAXWL; w++) {
+        uint32_t x = v[w];
+        if (32 * w + 31 < from) x = 0u;
+        else if (32 * w < from) x &= ~0u << (from - 32 * w);
+        if (x) return 32 * w + __builtin_ctz(x);
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int last_bit(const uint32_t (&v)[MAXWL])
+{
+#pragma unroll
+    for (int w = MAXWL - 1; w >= 0; w--)
+        if (v[w]) return 32 * w + 31 - __builtin_clz(v[w]);
+    return -1;
+}
+
 template <int ST, bool LAST, int V>
 __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
 {
@@ -342,32 +365,27 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
 
     for (int64_t it = (int64_t)blockIdx.x * 4 + wv; it < nitems; it += nwaves) {
         const Item item = D.items[it];
-        int tb = 0, te = 0;  // march range
+        // presence of the block along the pencil (wave-uniform), and the
+        // starts of gaps of at least 6 cells without it
+        uint32_t m[MAXWL], gap[MAXWL];
         // per-cell slot table of this item in LDS: slot, slot|NEWFLAG or ABSENT
         {
-            uint32_t m[MAXWL];
             int pre[MAXWL + 1];
             pre[0] = 0;
 #pragma unroll
             for (int w = 0; w < MAXWL; w++) {
-                m[w] = (w < WL) ? D.masks[it * D.wlmax + w] : 0u;
+                m[w] = (w < WL) ? __builtin_amdgcn_readfirstlane(D.masks[it * D.wlmax + w]) : 0u;
                 pre[w + 1] = pre[w] + __popc(m[w]);
             }
             if (pre[MAXWL] == 0) continue;
-            // the march covers the cells from the first holding the block to
-            // three past the last (where the last one is written): before the
-            // first, every cell reads as zero and the reconstruction state is
-            // the zero state the march starts from
-            tb = -1;
 #pragma unroll
             for (int w = 0; w < MAXWL; w++) {
-                if (m[w] != 0u) {
-                    if (tb < 0) tb = 32 * w + __builtin_ctz(m[w]);
-                    te = 32 * w + 31 - __builtin_clz(m[w]) + 4;
-                }
+                const uint32_t a0 = ~m[w], a1 = (w + 1 < MAXWL) ? ~m[w + 1] : ~0u;
+                uint32_t r = a0;
+#pragma unroll
+                for (int k = 1; k < 6; k++) r &= (a0 >> k) | (a1 << (32 - k));
+                gap[w] = r & ((m[w] << 1) | (w > 0 ? m[w - 1] >> 31 : 0u));
             }
-            tb = __builtin_amdgcn_readfirstlane(tb);
-            te = __builtin_amdgcn_readfirstlane(te);
             const int half = lane >> 5, b = lane & 31;
 #pragma unroll
             for (int w = 0; w < MAXWL; w += 2) {
@@ -391,12 +409,23 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
         const unsigned long long npos = __ballot(c > 0.0), nneg = __ballot(c < 0.0);
         double carry = 0.0;
         uint8_t *sflag = s_flag[wv];
-        if (npos == ~0ull)
-            march<ST, 1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
-        else if (nneg == ~0ull)
-            march<ST, -1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
-        else
-            march<ST, 0, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
+        // March each segment of cells holding the block: from its first such
+        // cell to three past its last (where the last one is written).  Before
+        // a segment's first cell at least 6 cells read as zero, so the
+        // reconstruction state there is the zero state a march starts from;
+        // the rounding carry runs on across segments.
+        int tb = first_bit(m, 0);
+        while (tb >= 0) {
+            const int g = first_bit(gap, tb + 1);
+            const int te = (g >= 0) ? g + 3 : last_bit(m) + 4;
+            if (npos == ~0ull)
+                march<ST, 1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
+            else if (nneg == ~0ull)
+                march<ST, -1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
+            else
+                march<ST, 0, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
+            tb = (g >= 0) ? first_bit(m, g) : -1;
+        }
         if constexpr (LAST) {
             // content flags of the written cells, one store per cell in parallel
             wave_sync_lds();

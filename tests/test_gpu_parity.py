@@ -218,3 +218,26 @@ def test_limited_ghost_translation_levels_match_oracle(sparse_small, k):
     compare_states(p.export(), o.export_local(), TOL64)
     for g, r in zip(gs, os_):
         assert g["updated_ps"] == r["updates"]
+
+
+def test_long_pencils_with_gaps_match_oracle_for_every_variant():
+    """Pencils 54 cells long whose blocks come and go at random, so the gaps
+    between the cells holding a block take every length: each shear variant
+    against the oracle, with the mass balance."""
+    n, nblk = (48, 4, 3), (2, 2, 2)
+    st = random_state(n, nblk, 77, density=0.3, zero_frac=0.0)
+    w = W.Workload("gaps", n, (4.0, 5.0, 7.0), nblk, (-4.0,) * 3, (1.0,) * 3, 1.0, 2, 0.0, 0,
+                   B.VL_F64, (0, 1, 2), *st)
+    print_case("long pencils with gaps, every variant")
+    o, _ = run_oracle(w, 2)
+    want = o.export_local()
+    for v in range(64):
+        p = gpu_partition(w)
+        try:
+            p.set_variant(v)
+        except B.VlasovError:
+            break
+        s = run_gpu(p, w.dt, 2, stats=True)
+        compare_states(p.export(), want, TOL64)
+        for x in s:
+            assert abs(x["mass_after"] + x["pruned_mass"] - x["mass_before"]) <= 1e-12 * x["mass_before"], v
