@@ -67,7 +67,7 @@ enum {
  * vl_init_partition; none may change afterwards). */
 typedef struct vl_desc {
     int32_t n[3];         /* local cells per axis, >= 1 each; n[d] + 6 <= 256 */
-    int32_t nblk[3];      /* velocity blocks per axis; product <= 131072 */
+    int32_t nblk[3];      /* velocity blocks per axis, each <= 1024; product <= 131072 */
     int32_t order[3];     /* shear order, a permutation of {0,1,2}; x->y->z = {0,1,2};
                              the paper's Z->X->Y = {2,0,1} */
     int32_t storage;      /* VL_F64, VL_F32 or VL_BF16 */

@@ -34,7 +34,7 @@ bool desc_ok(const vl_desc *d)
     int64_t nb = 1;
     for (int k = 0; k < 3; k++) {
         if (d->n[k] < 1 || d->n[k] + 2 * H > MAXL) return false;
-        if (d->nblk[k] < 1) return false;
+        if (d->nblk[k] < 1 || d->nblk[k] > 1024) return false;
         nb *= d->nblk[k];
         if (!(d->dx[k] > 0.0) || !(d->dv[k] > 0.0) || !isfinite(d->vmin[k])) return false;
         if (!isfinite(d->dx[k]) || !isfinite(d->dv[k])) return false;

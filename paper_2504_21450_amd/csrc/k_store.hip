@@ -361,9 +361,12 @@ __global__ __launch_bounds__(256) void k_moments(Dev D, double *dn, double *dV, 
     const double oz = ((lane >> 4) - 1.5) * D.dv[2] - rz;
     double s0 = 0.0, s1x = 0.0, s1y = 0.0, s1z = 0.0;
     double sxx = 0.0, syy = 0.0, szz = 0.0, sxy = 0.0, sxz = 0.0, syz = 0.0;
-    auto acc = [&](double f, int32_t b) {
-        double cx, cy, cz;
-        block_centre(D, b, cx, cy, cz);
+    // pk: the block's coordinates packed as bx | by << 10 | bz << 20 (each
+    // lane divides its own id once; the loop only unpacks broadcast words)
+    auto acc = [&](double f, int32_t pk) {
+        const double cx = D.vmin[0] + (4 * (pk & 1023) + 2) * D.dv[0];
+        const double cy = D.vmin[1] + (4 * ((pk >> 10) & 1023) + 2) * D.dv[1];
+        const double cz = D.vmin[2] + (4 * (pk >> 20) + 2) * D.dv[2];
         const double ux = cx + ox, uy = cy + oy, uz = cz + oz;
         const double fx = f * ux, fy = f * uy, fz = f * uz;
         s0 += f;
@@ -388,6 +391,8 @@ __global__ __launch_bounds__(256) void k_moments(Dev D, double *dn, double *dV, 
         const int ng = min(64, cnt - g);
         const int32_t myid = lane < ng ? D.lid[ls + g + lane] : 0;
         const int32_t myslot = lane < ng ? D.lslot[ls + g + lane] : 0;
+        const int32_t mypk = (myid % D.nblk[0]) | (((myid / D.nblk[0]) % D.nblk[1]) << 10) |
+                             ((myid / (D.nblk[0] * D.nblk[1])) << 20);
         int k = 0;
         for (; k + NF <= ng; k += NF) {
             T r[NF];
@@ -395,11 +400,11 @@ __global__ __launch_bounds__(256) void k_moments(Dev D, double *dn, double *dV, 
             for (int j = 0; j < NF; j++)
                 r[j] = pool[(int64_t)__builtin_amdgcn_readlane(myslot, k + j) * BLK + lane];
 #pragma unroll
-            for (int j = 0; j < NF; j++) acc(Storage<ST>::widen(r[j]), __builtin_amdgcn_readlane(myid, k + j));
+            for (int j = 0; j < NF; j++) acc(Storage<ST>::widen(r[j]), __builtin_amdgcn_readlane(mypk, k + j));
         }
         for (; k < ng; k++)
             acc(Storage<ST>::widen(pool[(int64_t)__builtin_amdgcn_readlane(myslot, k) * BLK + lane]),
-                __builtin_amdgcn_readlane(myid, k));
+                __builtin_amdgcn_readlane(mypk, k));
     }
     s0 = wave_sum(s0);
     s1x = wave_sum(s1x);

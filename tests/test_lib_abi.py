@@ -72,7 +72,7 @@ def test_workspace_bytes_and_descriptor_validation():
     bad = [dict(n=(0, 3, 5)), dict(n=(251, 3, 5)), dict(nblk=(0, 2, 2)), dict(order=(0, 0, 1)),
            dict(storage=3), dict(stencil=3), dict(gt_level=0), dict(gt_level=4), dict(vbuffer=7),
            dict(dx=(0.0, 1.0, 1.0)), dict(dv=(1.0, -1.0, 1.0)), dict(block_capacity=0),
-           dict(nblk=(64, 64, 64))]
+           dict(nblk=(64, 64, 64)), dict(nblk=(1025, 1, 1))]
     for kw in bad:
         assert B.workspace_bytes(good_desc(**kw)) == 0, kw
     for k in (1, 2, 3):  # Ghost Translation levels
