@@ -70,6 +70,8 @@ def lib():
         L.vlo_update_box.argtypes = [C.c_void_p, C.c_int32, C.c_int32, i32p, i32p]
         L.vlo_set_gt_level.restype = C.c_int32
         L.vlo_set_gt_level.argtypes = [C.c_void_p, C.c_int32]
+        L.vlo_set_edges.restype = C.c_int32
+        L.vlo_set_edges.argtypes = [C.c_void_p, C.c_int32]
         L.vlo_step.restype = C.c_int
         L.vlo_step.argtypes = [C.c_void_p, C.c_double, C.c_int32, f64p]
         L.vlo_local_mass.restype = C.c_double
@@ -191,6 +193,12 @@ class OraclePartition:
         later shears' ghost layers computed by each shear, 1..3."""
         if lib().vlo_set_gt_level(self._h, int(k)) != 0:
             raise ValueError("gt level must be 1, 2 or 3")
+
+    def set_edges(self, mask):
+        """Faces at the simulation edge (bit 2d low, 2d+1 high face of axis
+        d): the padded cells beyond them are boundary cells, kept as loaded."""
+        if lib().vlo_set_edges(self._h, int(mask)) != 0:
+            raise ValueError("edge mask must be in 0..63")
 
     def update_box(self, mode, s):
         lo = np.zeros(3, np.int32)

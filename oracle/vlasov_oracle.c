@@ -77,6 +77,7 @@ typedef struct {
     int32_t vbuffer;
     int32_t ghosts_valid;
     int32_t gt_level;  /* Ghost Translation level k = 1, 2, 3 (Section 3.2) */
+    int32_t edges;     /* faces at the simulation edge: bit 2d low, 2d+1 high face of axis d */
     vlo_cell *cells;   /* padded box, x fastest */
     double *cover[3];  /* optional Courant table override per axis (nv[d]) */
 } vlo_part;
@@ -375,6 +376,19 @@ static void copy_cell(vlo_part *p, int64_t dst, int64_t src)
     cell_assign(&p->cells[dst], s->n, s->ids, s->f);
 }
 
+/* A padded cell beyond a face at the simulation edge is a boundary cell
+ * (Section 2.1): it provides stencil data but is not translated, and ghost
+ * updates leave it as it was loaded. */
+static int beyond_edge(const vlo_part *p, int x, int y, int z)
+{
+    const int g[3] = {x, y, z};
+    for (int e = 0; e < 3; e++) {
+        if (g[e] < VLO_H && (p->edges >> (2 * e) & 1)) return 1;
+        if (g[e] >= VLO_H + p->n[e] && (p->edges >> (2 * e + 1) & 1)) return 1;
+    }
+    return 0;
+}
+
 /* Coalesced ghost update: every padded cell outside the local box becomes a
  * copy of its periodic image (Section 3, Fig. 3a). */
 void vlo_fill_ghosts(void *h)
@@ -383,7 +397,7 @@ void vlo_fill_ghosts(void *h)
     for (int z = 0; z < p->P[2]; z++)
         for (int y = 0; y < p->P[1]; y++)
             for (int x = 0; x < p->P[0]; x++) {
-                if (is_local(p, x, y, z)) continue;
+                if (is_local(p, x, y, z) || beyond_edge(p, x, y, z)) continue;
                 copy_cell(p, cidx(p, x, y, z),
                           cidx(p, wrap(x, p->n[0]), wrap(y, p->n[1]), wrap(z, p->n[2])));
             }
@@ -412,7 +426,7 @@ static void fill_faces(vlo_part *p, int d)
     for (int z = lo[2]; z < hi[2]; z++)
         for (int y = lo[1]; y < hi[1]; y++)
             for (int x = lo[0]; x < hi[0]; x++) {
-                if (is_local(p, x, y, z)) continue;
+                if (is_local(p, x, y, z) || beyond_edge(p, x, y, z)) continue;
                 copy_cell(p, cidx(p, x, y, z),
                           cidx(p, wrap(x, p->n[0]), wrap(y, p->n[1]), wrap(z, p->n[2])));
             }
@@ -542,7 +556,8 @@ static void sweep(vlo_part *p, int d, const int lo[3], const int hi[3], double d
  * since those cells feed the later stencils (Section 3.1); Ghost Translation
  * of level k computes only the k layers nearest the local domain and leaves
  * the others at their ghost-update values (Section 3.2: GT3 all three, GT1
- * one).  Classical: the local box. */
+ * one); a domain at the simulation edge needs no layers there (Section 3.3).
+ * Classical: the local box. */
 void vlo_update_box(void *h, int32_t mode, int32_t s, int32_t *lo, int32_t *hi)
 {
     vlo_part *p = (vlo_part *)h;
@@ -553,9 +568,21 @@ void vlo_update_box(void *h, int32_t mode, int32_t s, int32_t *lo, int32_t *hi)
     if (mode == VLO_COALESCED)
         for (int t = s + 1; t < 3; t++) {
             int e = p->order[t];
-            lo[e] = VLO_H - p->gt_level;
-            hi[e] = VLO_H + p->n[e] + p->gt_level;
+            /* no ghost layers are translated beyond a simulation edge */
+            lo[e] = (p->edges >> (2 * e) & 1) ? VLO_H : VLO_H - p->gt_level;
+            hi[e] = (p->edges >> (2 * e + 1) & 1) ? VLO_H + p->n[e] : VLO_H + p->n[e] + p->gt_level;
         }
+}
+
+/* Faces at the simulation edge (bit 2d: low face of axis d, bit 2d+1: high
+ * face); the padded cells beyond them are boundary cells.  Returns 0, or -1
+ * for a mask outside 0..63. */
+int32_t vlo_set_edges(void *h, int32_t mask)
+{
+    vlo_part *p = (vlo_part *)h;
+    if (mask < 0 || mask > 63) return -1;
+    p->edges = mask;
+    return 0;
 }
 
 /* Ghost Translation level of the coalesced mode: 1, 2 or 3 (default 3).
