@@ -78,7 +78,14 @@ typedef struct vl_desc {
                              2 (GT2) leave the outer layers at their ghost-update values */
     int32_t vbuffer;      /* velocity-space buffer kept around content blocks:
                              0, 6 (face neighbours) or 26 (all neighbours) */
-    int32_t reserved0;    /* must be 0 */
+    int32_t edges;        /* faces at the simulation edge, bit 2d: low face of axis d,
+                             bit 2d+1: high face (0 = periodic or interior everywhere).
+                             The ghost layers beyond such a face are boundary cells
+                             (Section 2.1): they feed the stencils but are not
+                             translated, so no Ghost Translation layers are computed
+                             there (Section 3.3); their contents come from the sources
+                             given to vl_fill_ghosts_from (vl_fill_ghosts is then an
+                             error). */
     double dx[3];         /* spatial cell size [m], > 0 */
     double vmin[3];       /* lower edge of the velocity mesh [m/s] */
     double dv[3];         /* velocity cell size [m/s], > 0 */
@@ -140,7 +147,8 @@ int vl_load_values(vl_partition *p, int64_t first_block, int64_t nblocks, const 
 
 /* Coalesced ghost update (Section 3, Fig. 3a): every cell of the padded box
  * outside the local box receives the block list and values of its periodic
- * image.  Once per step, before a VL_COALESCED step.  Asynchronous. */
+ * image.  Once per step, before a VL_COALESCED step.  Asynchronous.
+ * VL_ERR_ARG if desc.edges is set (boundary cells need their sources). */
 int vl_fill_ghosts(vl_partition *p);
 
 /* Coalesced ghost update from neighbouring partitions (Section 3, Fig. 3a:
@@ -151,7 +159,11 @@ int vl_fill_ghosts(vl_partition *p);
  * local box (each side >= 3 cells), velocity mesh and storage, and live on the
  * same device (or are readable from it).  The neighbours' local cells are read
  * on p's stream: the caller orders their previous steps before this call and
- * this call before their next steps.  Asynchronous.
+ * this call before their next steps.  The partition keeps these sources for
+ * its per-sweep face refreshes and its graph-recorded ghost updates.  Beyond
+ * a simulation edge (desc.edges) the source is a partition that is never
+ * stepped, whose cells hold the boundary cells' fixed contents.
+ * Asynchronous.
  * Errors: VL_ERR_ARG (mismatch, NULL, nbr[13] != p), VL_ERR_STATE, VL_ERR_HIP. */
 int vl_fill_ghosts_from(vl_partition *p, vl_partition *const *nbr);
 
@@ -160,7 +172,9 @@ int vl_fill_ghosts_from(vl_partition *p, vl_partition *const *nbr);
  * v dt / dx[d], followed by block pruning of the local cells.
  *   mode VL_COALESCED: Ghost Translation; needs vl_fill_ghosts since the
  *        last step (else VL_ERR_STALE_GHOSTS).
- *   mode VL_PER_SWEEP: classical per-direction ghost refresh (Fig. 1).
+ *   mode VL_PER_SWEEP: classical per-direction ghost refresh (Fig. 1), from
+ *        the sources of the last vl_fill_ghosts_from if there was one
+ *        (required when desc.edges is set), else from periodic images.
  * Both modes give the same local result bit for bit.  The ghost domain is
  * stale afterwards.  dt > 0 [s].  stats: optional host output; if non-NULL
  * the call synchronises and also reports device-side errors.
@@ -176,6 +190,8 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
  * plus vl_translate_step.  The graphs are cached per starting list region
  * and re-recorded when dt, mode, shear variant or Courant override change;
  * recording uses a private stream, replays go to the partition's stream.
+ * The recorded ghost update uses the sources of the last vl_fill_ghosts_from
+ * if there was one (required when desc.edges is set), else periodic images.
  * Asynchronous: device-side errors surface at the next synchronising call.
  * The ghost domain is stale afterwards.  nsteps >= 0.
  * Errors: VL_ERR_ARG, VL_ERR_CFL, VL_ERR_STATE, VL_ERR_HIP. */

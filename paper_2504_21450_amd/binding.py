@@ -29,7 +29,7 @@ EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_load_values", "vl_fil
 class VlDesc(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("nblk", C.c_int32 * 3), ("order", C.c_int32 * 3),
                 ("storage", C.c_int32), ("stencil", C.c_int32), ("gt_level", C.c_int32),
-                ("vbuffer", C.c_int32), ("reserved0", C.c_int32),
+                ("vbuffer", C.c_int32), ("edges", C.c_int32),
                 ("dx", C.c_double * 3), ("vmin", C.c_double * 3), ("dv", C.c_double * 3),
                 ("sparse_min", C.c_double), ("block_capacity", C.c_int64),
                 ("ghost_block_capacity", C.c_int64)]
@@ -120,12 +120,13 @@ def _ptr(a):
 
 
 def make_desc(n, nblk, dx, vmin, dv, order=(0, 1, 2), storage=VL_F64, sparse_min=0.0, vbuffer=0,
-              block_capacity=1, ghost_block_capacity=1, stencil=2, gt_level=3):
+              block_capacity=1, ghost_block_capacity=1, stencil=2, gt_level=3, edges=0):
     d = VlDesc()
     for k in range(3):
         d.n[k], d.nblk[k], d.order[k] = int(n[k]), int(nblk[k]), int(order[k])
         d.dx[k], d.vmin[k], d.dv[k] = float(dx[k]), float(vmin[k]), float(dv[k])
-    d.storage, d.stencil, d.gt_level, d.vbuffer, d.reserved0 = int(storage), int(stencil), int(gt_level), int(vbuffer), 0
+    d.storage, d.stencil, d.gt_level, d.vbuffer = int(storage), int(stencil), int(gt_level), int(vbuffer)
+    d.edges = int(edges)
     d.sparse_min = float(sparse_min)
     d.block_capacity = int(block_capacity)
     d.ghost_block_capacity = int(ghost_block_capacity)
@@ -149,7 +150,7 @@ class Partition:
 
     def __init__(self, n, nblk, dx, vmin, dv, offsets, ids, f, storage=VL_F64, order=(0, 1, 2),
                  sparse_min=0.0, vbuffer=0, block_capacity=None, ghost_block_capacity=None,
-                 device="cuda:0", slack=2.5, gt_level=3):
+                 device="cuda:0", slack=2.5, gt_level=3, edges=0):
         import torch
 
         self.torch = torch
@@ -173,7 +174,7 @@ class Partition:
             if nghost * NB <= 20_000_000:
                 ghost_block_capacity = max(ghost_block_capacity, nghost * NB + 1024)
         self.desc = make_desc(n, nblk, dx, vmin, dv, order, storage, sparse_min, vbuffer,
-                              block_capacity, ghost_block_capacity, gt_level=gt_level)
+                              block_capacity, ghost_block_capacity, gt_level=gt_level, edges=edges)
         self.ws_bytes = workspace_bytes(self.desc)
         if self.ws_bytes == 0:
             raise VlasovError("vl_workspace_bytes", VL_ERR_ARG)

@@ -49,7 +49,7 @@ bool desc_ok(const vl_desc *d)
     if (d->storage != VL_F64 && d->storage != VL_F32 && d->storage != VL_BF16) return false;
     if (d->stencil != 2 || d->gt_level < 1 || d->gt_level > H) return false;
     if (d->vbuffer != 0 && d->vbuffer != 6 && d->vbuffer != 26) return false;
-    if (d->reserved0 != 0) return false;
+    if (d->edges < 0 || d->edges > 63) return false;
     if (!isfinite(d->sparse_min)) return false;
     if (d->block_capacity < 1 || d->ghost_block_capacity < 1) return false;
     // slots (and the scratch slot) must stay below the row flag bit
@@ -122,6 +122,8 @@ struct GraphCache {
 struct vl_partition {
     Prof prof;
     GraphCache graph;
+    SrcTable src;       // ghost sources of the last vl_fill_ghosts_from (per-sweep face fills use them)
+    bool has_src;
     vl_desc desc;
     Layout lay;
     Dev D;
@@ -207,11 +209,11 @@ void update_box(const vl_partition *p, int mode, int s, int lo[3], int hi[3])
         lo[e] = H;
         hi[e] = H + p->desc.n[e];
     }
-    if (mode == VL_COALESCED)  // the later axes' ghost layers within the GT level
-        for (int t = s + 1; t < 3; t++) {
-            int e = p->desc.order[t];
-            lo[e] = H - p->desc.gt_level;
-            hi[e] = H + p->desc.n[e] + p->desc.gt_level;
+    if (mode == VL_COALESCED)  // the later axes' ghost layers within the GT level,
+        for (int t = s + 1; t < 3; t++) {  // none beyond a simulation edge
+            const int e = p->desc.order[t], ed = p->desc.edges;
+            lo[e] = (ed >> (2 * e) & 1) ? H : H - p->desc.gt_level;
+            hi[e] = (ed >> (2 * e + 1) & 1) ? H + p->desc.n[e] : H + p->desc.n[e] + p->desc.gt_level;
         }
 }
 
@@ -238,7 +240,10 @@ void enqueue_translate(vl_partition *p, double dt, int mode, double *ledger, hip
             fhi[d] = D.P[d];
             launch_book(D, BOOK_GHOST_RESET, st);
             ProfScope ps(p, K_FILL);
-            launch_fill(D, flo, fhi, st);
+            if (p->has_src)
+                launch_fill_box(D, p->src, flo, fhi, st);
+            else
+                launch_fill(D, flo, fhi, st);
         }
         launch_book(D, BOOK_SWEEP_RESET, st);
         {
@@ -264,7 +269,10 @@ void enqueue_fill(vl_partition *p, hipStream_t st)
     int lo[3] = {0, 0, 0}, hi[3] = {D.P[0], D.P[1], D.P[2]};
     launch_book(D, BOOK_GHOST_RESET, st);
     ProfScope ps(p, K_FILL);
-    launch_fill(D, lo, hi, st);
+    if (p->has_src)  // the sources of the last vl_fill_ghosts_from
+        launch_fill_from(D, p->src, st);
+    else
+        launch_fill(D, lo, hi, st);
 }
 
 void drop_graphs(vl_partition *p)
@@ -363,6 +371,7 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
     p->cur = 0;
     p->init_blocks = total;
     p->loadable = true;
+    p->has_src = false;
     p->ghosts_valid = false;
     p->bad = false;
     p->has_cover = false;
@@ -534,6 +543,9 @@ int vl_fill_ghosts(vl_partition *p)
 {
     if (!p) return VL_ERR_ARG;
     if (p->bad) return VL_ERR_STATE;
+    if (p->desc.edges) return VL_ERR_ARG;  // boundary cells need their sources
+    if (p->has_src) drop_graphs(p);
+    p->has_src = false;
     enqueue_fill(p, p->stream);
     VL_HIP(hipGetLastError());
     p->ghosts_valid = true;
@@ -566,6 +578,9 @@ int vl_fill_ghosts_from(vl_partition *p, vl_partition *const *nbr)
         launch_fill_from(p->D, src, p->stream);
     }
     VL_HIP(hipGetLastError());
+    p->src = src;
+    p->has_src = true;
+    drop_graphs(p);
     p->ghosts_valid = true;
     return VL_OK;
 }
@@ -578,6 +593,7 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
     if (!(dt > 0.0) || !isfinite(dt)) return VL_ERR_ARG;
     if (check_cfl(p, dt)) return VL_ERR_CFL;
     if (mode == VL_COALESCED && !p->ghosts_valid) return VL_ERR_STALE_GHOSTS;
+    if (mode == VL_PER_SWEEP && p->desc.edges && !p->has_src) return VL_ERR_STALE_GHOSTS;
     const Dev &D = p->D;
     hipStream_t st = p->stream;
     if (stats) {
@@ -633,6 +649,7 @@ int vl_graph_step(vl_partition *p, double dt, int32_t mode, int32_t nsteps)
     if (mode != VL_COALESCED && mode != VL_PER_SWEEP) return VL_ERR_ARG;
     if (!(dt > 0.0) || !isfinite(dt)) return VL_ERR_ARG;
     if (check_cfl(p, dt)) return VL_ERR_CFL;
+    if (p->desc.edges && !p->has_src) return VL_ERR_STALE_GHOSTS;
     GraphCache &g = p->graph;
     if (g.dt != dt || g.mode != mode || g.variant != p->D.sweep_variant) {
         drop_graphs(p);

@@ -215,6 +215,11 @@ static void launch_fill_any(const Dev &D, const SrcTable &src, const int lo[3], 
     }
 }
 
+void launch_fill_box(const Dev &D, const SrcTable &src, const int lo[3], const int hi[3], hipStream_t st)
+{
+    launch_fill_any(D, src, lo, hi, st);
+}
+
 void launch_fill_from(const Dev &D, const SrcTable &src, hipStream_t st)
 {
     const int lo[3] = {0, 0, 0}, hi[3] = {D.P[0], D.P[1], D.P[2]};

@@ -151,6 +151,7 @@ struct SrcTable {
 };
 void launch_fill(const Dev &D, const int lo[3], const int hi[3], hipStream_t st);
 void launch_fill_from(const Dev &D, const SrcTable &src, hipStream_t st);
+void launch_fill_box(const Dev &D, const SrcTable &src, const int lo[3], const int hi[3], hipStream_t st);
 SrcPart self_source(const Dev &D);
 void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, int cur,
                  hipStream_t st);
