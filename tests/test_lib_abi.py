@@ -106,3 +106,20 @@ def test_null_handles_are_rejected():
     assert lib.vl_translate_step(None, 1.0, 0, None) == B.VL_ERR_ARG
     assert lib.vl_sync(None) == B.VL_ERR_ARG
     lib.vl_destroy(None)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library the binding raises instead of falling back."""
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libvlasov.so"))
+    with pytest.raises(RuntimeError):
+        B.load()
+
+
+def test_edges_field_takes_the_reserved_slot():
+    """The simulation-edge mask sits where the header's descriptor has it and
+    only six face bits are accepted."""
+    assert B.VlDesc.edges.offset == B.VlDesc.vbuffer.offset + 4
+    assert B.workspace_bytes(good_desc(edges=63)) > 0
+    assert B.workspace_bytes(good_desc(edges=64)) == 0
+    assert B.workspace_bytes(good_desc(edges=-1)) == 0
