@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--storage", default="f64", choices=sorted(STORAGES))
     ap.add_argument("--mode", default="coalesced", choices=["coalesced", "per_sweep"])
+    ap.add_argument("--order", default="xyz", choices=["xyz", "zxy", "yzx"],
+                    help="shear order (the paper's is zxy)")
     ap.add_argument("--gt-level", type=int, default=3, choices=[1, 2, 3],
                     help="Ghost Translation level of the coalesced mode (3 = exact)")
     ap.add_argument("--workload", default="maxwellian", choices=["maxwellian", "mixture"])
@@ -169,12 +171,14 @@ def main():
             del pp
             torch.cuda.empty_cache()
         w = W.blob_mixture(n=n, hot_fraction=args.hot, sample=False, storage=STORAGES[args.storage])
+        w.order = tuple("xyz".index(a) for a in args.order)
         p = devsample.sample_partition(w, slack=slack, gt_level=args.gt_level)
         if tune is not None:
             p.set_variant(tune["variant"])
     else:
         w = W.maxwellian_sparse(n=n, threads=min(16, os.cpu_count() or 1))
         w.storage = STORAGES[args.storage]
+        w.order = tuple("xyz".index(a) for a in args.order)
         p = B.Partition.from_workload(w, slack=slack, gt_level=args.gt_level)
     log("generated %d blocks (%.3e phase-space cells) in %.1f s"
         % (w.nblocks, w.nblocks * 64.0, time.time() - t0))
@@ -236,7 +240,8 @@ def main():
     per_launch = shear_bytes / max(shear_n, 1)
     avg_launch_s = shear_ms / max(shear_n, 1) / 1e3
     achieved = per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(args.storage, variant, w.name) if args.gt_level == 3 else None
+    traffic = (measured_traffic(args.storage, variant, w.name)
+               if args.gt_level == 3 and args.order == "xyz" and args.mode == "coalesced" else None)
 
     out = {
         "metric": METRIC,
@@ -251,9 +256,10 @@ def main():
         "vs_baseline": None,
         "dtype": args.storage,
         "data": "synthetic",
-        "config": {"workload": "%s coalesced-ghost sparse translation (%s storage, %s mode%s)"
+        "config": {"workload": "%s coalesced-ghost sparse translation (%s storage, %s mode%s%s)"
                                % (w.name, args.storage, args.mode,
-                                  "" if args.gt_level == 3 else ", GT%d" % args.gt_level),
+                                  "" if args.gt_level == 3 else ", GT%d" % args.gt_level,
+                                  "" if args.order == "xyz" else ", %s order" % args.order),
                    "cells": list(n), "velocity_cells": [4 * b for b in w.nblk],
                    "local_blocks": int(blocks1), "local_ps_cells": int(blocks1 * 64),
                    "blocks_per_cell": [int(v) for v in np.percentile(np.diff(w.offsets), [0, 50, 100])],
