@@ -44,17 +44,31 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def variant_key(v):
+    """'a,b,c': the shear variants of the first, second and third shear."""
+    return ",".join(str(int(x)) for x in (v if isinstance(v, (tuple, list)) else (v, v, v)))
+
+
+def parse_variant(s):
+    v = [int(x) for x in s.split(",")]
+    if len(v) == 1:
+        return v[0]
+    if len(v) != 3:
+        raise argparse.ArgumentTypeError("one variant or three (first,second,third shear)")
+    return tuple(v)
+
+
 def measured_traffic(storage, variant, workload):
     """HBM bytes per shear launch from the committed rocprofv3 counter runs of
     the same command, if they were taken on the current kernel source with the
-    same shear variant; else None."""
+    same shear variants; else None."""
     path = os.path.join(ROOT, "profiles", "shear_traffic_%s.json" % storage)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("workload") != workload:
         return None
-    return d.get("hbm_bytes_per_launch", {}).get(str(variant))
+    return d.get("hbm_bytes_per_launch", {}).get(variant_key(variant))
 
 
 def cpu_baseline(w, sample, min_seconds=10.0, max_steps=40):
@@ -123,8 +137,9 @@ def main():
                          "for the mixture; the smooth case spreads by ~0.7 %% of blocks per step)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the shear-kernel autotuner (it runs real steps before warmup)")
-    ap.add_argument("--variant", type=int, default=None,
-                    help="shear variant for the timed steps (the autotuner's steps still run unless "
+    ap.add_argument("--variant", type=parse_variant, default=None,
+                    help="shear variant for the timed steps, one for all shears or 'a,b,c' for the "
+                         "first, second and third (the autotuner's steps still run unless "
                          "--no-autotune, so the state evolves as in a default run)")
     ap.add_argument("--graph-steps", type=int, default=None,
                     help="steps replayed from recorded HIP graphs after the timed region "
@@ -165,8 +180,8 @@ def main():
             best, ms = pp.autotune(wp.dt, B.VL_COALESCED if args.mode == "coalesced" else B.VL_PER_SWEEP,
                                    steps_per_variant=2)
             tune = {"variant": best, "shear_ms_per_step": ms, "proxy": "x".join(map(str, proxy_n))}
-            log("autotune on %s: variant %d, shear ms/step per variant %s"
-                % (tune["proxy"], best, ["%.2f" % v for v in ms]))
+            log("autotune on %s: variants %s, shear ms/step per variant %s"
+                % (tune["proxy"], variant_key(best), ["%.2f" % v for v in ms]))
             pp.close()
             del pp
             torch.cuda.empty_cache()
@@ -204,7 +219,7 @@ def main():
     if args.autotune and not mixture:
         best, ms = p.autotune(w.dt, mode, steps_per_variant=2)
         tune = {"variant": best, "shear_ms_per_step": ms}
-        log("autotune: variant %d, shear ms/step per variant %s" % (best, ["%.2f" % v for v in ms]))
+        log("autotune: variants %s, shear ms/step per variant %s" % (variant_key(best), ["%.2f" % v for v in ms]))
     variant = tune["variant"] if tune else 0
     if args.variant is not None:
         p.set_variant(args.variant)
@@ -266,7 +281,7 @@ def main():
                    "dt_over_dx_max_courant": w.max_courant()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sweep (PPM shear), variant %d" % variant,
+                     "kernel": "k_sweep (PPM shear), variants %s" % variant_key(variant),
                      "algorithmic_bytes_per_launch": per_launch,
                      "avg_launch_ms": 1e3 * avg_launch_s, "launches": shear_n},
         "computed_updates_per_s": computed / elapsed,

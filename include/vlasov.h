@@ -245,19 +245,32 @@ int vl_profile_start(vl_partition *p, int32_t max_launches);
 int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches);
 
 /* Autotuner (Section 2.1's shear, kernel shapes only): runs steps_per_variant
- * real translation steps (each with its ghost update in VL_COALESCED mode)
- * with every compiled variant of the shear kernel (store scheme, prefetch
- * depth, occupancy target), times the shear launches with HIP events on the
- * partition's stream, and keeps the fastest for the following steps.  All
- * variants compute bit-identical results, so the state advances exactly as
- * with ordinary steps.  *best receives the chosen variant; ms_out (optional,
- * ms_cap entries) the shear milliseconds per step of each variant.
+ * rounds of real translation steps (each with its ghost update in
+ * VL_COALESCED mode), one step with every compiled variant of the shear kernel
+ * (store scheme, prefetch depth, occupancy target) per round, times each
+ * shear launch with HIP events on the
+ * partition's stream, and keeps for each of the three shears of the order
+ * the variant that was fastest on it (the third shear, which also records
+ * the blocks' content flags, has kernels of its own with other register
+ * needs).  All variants compute bit-identical results, so the state advances
+ * exactly as with ordinary steps.  best[3] receives the chosen variant of the
+ * first, second and third shear; ms_out (optional, ms_cap entries) the
+ * milliseconds per step of all three shears with each variant.
  * Synchronises.  Errors as vl_translate_step. */
-int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_variant, int32_t *best,
+int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_variant, int32_t best[3],
                 double *ms_out, int32_t ms_cap);
 
-/* Select a shear-kernel variant explicitly (0 .. number of variants - 1). */
+/* Select one shear-kernel variant (0 .. number of variants - 1) for all
+ * three shears.  VL_ERR_ARG outside that range. */
 int vl_set_variant(vl_partition *p, int32_t variant);
+
+/* Select the variant of each shear of the order (first, second, third);
+ * VL_ERR_ARG (nothing changed) if any is outside 0 .. number of variants - 1. */
+int vl_set_shear_variants(vl_partition *p, const int32_t variants[3]);
+
+/* The variants in use for the three shears; *count (optional) receives the
+ * number of compiled variants.  Does not touch the device. */
+int vl_get_shear_variants(const vl_partition *p, int32_t variants[3], int32_t *count);
 
 /* Wait for the partition's stream and report device-side errors. */
 int vl_sync(vl_partition *p);

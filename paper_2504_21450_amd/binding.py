@@ -22,7 +22,8 @@ VL_OK, VL_ERR_ARG, VL_ERR_CFL, VL_ERR_CAPACITY, VL_ERR_STALE_GHOSTS, VL_ERR_HIP,
 EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_load_values", "vl_fill_ghosts", "vl_fill_ghosts_from", "vl_translate_step",
             "vl_moments", "vl_local_block_count", "vl_export_state", "vl_export_cells",
             "vl_set_courant_override", "vl_counters", "vl_profile_start", "vl_profile_stop",
-            "vl_autotune", "vl_set_variant", "vl_graph_step", "vl_sync", "vl_destroy",
+            "vl_autotune", "vl_set_variant", "vl_set_shear_variants", "vl_get_shear_variants",
+            "vl_graph_step", "vl_sync", "vl_destroy",
             "vl_status_string")
 
 
@@ -94,6 +95,10 @@ def load():
     L.vl_autotune.argtypes = [vp, dbl, i32, i32, vp, vp, i32]
     L.vl_set_variant.restype = C.c_int
     L.vl_set_variant.argtypes = [vp, i32]
+    L.vl_set_shear_variants.restype = C.c_int
+    L.vl_set_shear_variants.argtypes = [vp, vp]
+    L.vl_get_shear_variants.restype = C.c_int
+    L.vl_get_shear_variants.argtypes = [vp, vp, vp]
     L.vl_graph_step.restype = C.c_int
     L.vl_graph_step.argtypes = [vp, dbl, i32, i32]
     L.vl_sync.restype = C.c_int
@@ -278,16 +283,31 @@ class Partition:
         return {k: (float(a), int(c)) for k, a, c in zip(self.KERNEL_CLASSES, ms, n)}
 
     def autotune(self, dt, mode=VL_COALESCED, steps_per_variant=2):
-        """Time every shear-kernel variant on real steps and keep the fastest.
-        Returns (best variant, shear ms per step of each variant)."""
-        best = np.zeros(1, np.int32)
+        """Time every shear-kernel variant on real steps and keep the fastest
+        for each shear of the order.  Returns (the three chosen variants,
+        ms per step of all shears with each variant)."""
+        best = np.zeros(3, np.int32)
         ms = np.full(32, np.nan)
         _check("vl_autotune", self.lib.vl_autotune(self.h, float(dt), int(mode), int(steps_per_variant),
                                                    _ptr(best), _ptr(ms), 32))
-        return int(best[0]), [float(v) for v in ms if not np.isnan(v)]
+        return tuple(int(v) for v in best), [float(v) for v in ms if not np.isnan(v)]
 
     def set_variant(self, v):
-        _check("vl_set_variant", self.lib.vl_set_variant(self.h, int(v)))
+        """One variant for all three shears, or a sequence of three."""
+        if np.ndim(v) == 0:
+            _check("vl_set_variant", self.lib.vl_set_variant(self.h, int(v)))
+        else:
+            a = np.ascontiguousarray(v, np.int32)
+            if a.shape != (3,):
+                raise ValueError("three shear variants expected")
+            _check("vl_set_shear_variants", self.lib.vl_set_shear_variants(self.h, _ptr(a)))
+
+    def variants(self):
+        """(variants of the three shears, number of compiled variants)"""
+        a = np.zeros(3, np.int32)
+        n = np.zeros(1, np.int32)
+        _check("vl_get_shear_variants", self.lib.vl_get_shear_variants(self.h, _ptr(a), _ptr(n)))
+        return tuple(int(v) for v in a), int(n[0])
 
     def sync(self):
         _check("vl_sync", self.lib.vl_sync(self.h))

@@ -22,7 +22,7 @@ constexpr int RED_DOUBLES = 1024;
 inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t pool, ring, flags, lstart, lcount, lcapa, lsorted, lid, lslot, rows, items, masks, ctl, cover, cellred,
+    size_t pool, ring, lstart, lcount, lcapa, lsorted, lid, lslot, litem, rows, items, masks, ctl, cover, cellred,
         red, cellcnt, total;
     int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap;
     int wlmax, cover_stride;
@@ -79,7 +79,6 @@ Layout make_layout(const vl_desc *d)
     size_t o = 0;
     L.pool = o;    o = align_up(o + (size_t)(tot + 1 + NSINK) * BLK * bs);  // + zero block + sinks
     L.ring = o;    o = align_up(o + (size_t)lcap * 4);
-    L.flags = o;   o = align_up(o + (size_t)lcap);
     L.lstart = o;  o = align_up(o + (size_t)L.N * 8);
     L.lcount = o;  o = align_up(o + (size_t)L.N * 4);
     L.lcapa = o;   o = align_up(o + (size_t)L.N * 4);
@@ -87,6 +86,7 @@ Layout make_layout(const vl_desc *d)
     const size_t nl = (size_t)(2 * L.LA + L.LG);
     L.lid = o;     o = align_up(o + nl * 4);
     L.lslot = o;   o = align_up(o + nl * 4);
+    L.litem = o;   o = align_up(o + nl * 4);
     L.rows = o;    o = align_up(o + (size_t)L.row_cap * 4);
     L.items = o;   o = align_up(o + (size_t)L.item_cap * sizeof(Item));
     L.masks = o;   o = align_up(o + (size_t)L.item_cap * L.wlmax * 4);
@@ -116,7 +116,8 @@ struct GraphCache {
     hipStream_t cap = nullptr;  // private stream, used only to record captures
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     double dt = 0.0;
-    int mode = -1, variant = -1;
+    int mode = -1;
+    int variant[3] = {-1, -1, -1};
 };
 
 struct vl_partition {
@@ -258,7 +259,7 @@ void enqueue_translate(vl_partition *p, double dt, int mode, double *ledger, hip
     launch_book(D, nxt == 0 ? BOOK_PRUNE_RESET_A : BOOK_PRUNE_RESET_B, st);
     {
         ProfScope ps(p, K_PRUNE);
-        launch_prune(D, nxt, st);
+        launch_prune(D, nxt, p->desc.order[2], st);
     }
 }
 
@@ -283,7 +284,8 @@ void drop_graphs(vl_partition *p)
             (void)hipGraphExecDestroy(e);
             e = nullptr;
         }
-    g.mode = g.variant = -1;
+    g.mode = -1;
+    for (int &v : g.variant) v = -1;
 }
 
 // Record the step that starts from list region p->cur into g.exec[p->cur].
@@ -402,13 +404,13 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
     D.gcap = d->ghost_block_capacity;
     D.trash = D.lcap + D.gcap;
     D.ring = (int32_t *)(w + L.ring);
-    D.flags = (uint8_t *)(w + L.flags);
     D.lstart = (int64_t *)(w + L.lstart);
     D.lcount = (int32_t *)(w + L.lcount);
     D.lcapa = (int32_t *)(w + L.lcapa);
     D.lsorted = (int32_t *)(w + L.lsorted);
     D.lid = (int32_t *)(w + L.lid);
     D.lslot = (int32_t *)(w + L.lslot);
+    D.litem = (int32_t *)(w + L.litem);
     D.reg_off[0] = 0;
     D.reg_cap[0] = L.LA;
     D.reg_off[1] = L.LA;
@@ -472,7 +474,6 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
             if (hipMemcpy(D.lid, lid.data(), lid.size() * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
             if (hipMemcpy(D.lslot, lslot.data(), lslot.size() * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
         }
-        if (hipMemset(D.flags, 0, (size_t)D.lcap) != hipSuccess) { rc = VL_ERR_HIP; break; }
         // the scratch block reads as zero in the shears
         if (hipMemset((char *)D.pool + (size_t)D.trash * BLK * storage_bytes(d->storage), 0,
                       (size_t)BLK * storage_bytes(d->storage)) != hipSuccess) { rc = VL_ERR_HIP; break; }
@@ -651,11 +652,12 @@ int vl_graph_step(vl_partition *p, double dt, int32_t mode, int32_t nsteps)
     if (check_cfl(p, dt)) return VL_ERR_CFL;
     if (p->desc.edges && !p->has_src) return VL_ERR_STALE_GHOSTS;
     GraphCache &g = p->graph;
-    if (g.dt != dt || g.mode != mode || g.variant != p->D.sweep_variant) {
+    const int *sv = p->D.sweep_variant;
+    if (g.dt != dt || g.mode != mode || g.variant[0] != sv[0] || g.variant[1] != sv[1] || g.variant[2] != sv[2]) {
         drop_graphs(p);
         g.dt = dt;
         g.mode = mode;
-        g.variant = p->D.sweep_variant;
+        for (int s = 0; s < 3; s++) g.variant[s] = sv[s];
     }
     for (int k = 0; k < nsteps; k++) {
         if (!g.exec[p->cur]) {
@@ -749,39 +751,60 @@ int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches)
 int vl_set_variant(vl_partition *p, int32_t variant)
 {
     if (!p || variant < 0 || variant >= sweep_variants()) return VL_ERR_ARG;
-    p->D.sweep_variant = variant;
+    for (int s = 0; s < 3; s++) p->D.sweep_variant[s] = variant;
     drop_graphs(p);
     return VL_OK;
 }
 
-int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_variant, int32_t *best,
+int vl_set_shear_variants(vl_partition *p, const int32_t variants[3])
+{
+    if (!p || !variants) return VL_ERR_ARG;
+    for (int s = 0; s < 3; s++)
+        if (variants[s] < 0 || variants[s] >= sweep_variants()) return VL_ERR_ARG;
+    for (int s = 0; s < 3; s++) p->D.sweep_variant[s] = variants[s];
+    drop_graphs(p);
+    return VL_OK;
+}
+
+int vl_get_shear_variants(const vl_partition *p, int32_t variants[3], int32_t *count)
+{
+    if (!p || !variants) return VL_ERR_ARG;
+    for (int s = 0; s < 3; s++) variants[s] = p->D.sweep_variant[s];
+    if (count) *count = sweep_variants();
+    return VL_OK;
+}
+
+int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_variant, int32_t best[3],
                 double *ms_out, int32_t ms_cap)
 {
     if (!p || steps_per_variant < 1 || !best) return VL_ERR_ARG;
     if (p->bad) return VL_ERR_STATE;
     const int nv = sweep_variants();
-    double best_ms = 0.0;
-    int best_v = 0;
-    for (int v = 0; v < nv; v++) {
-        p->D.sweep_variant = v;
-        int rc = vl_profile_start(p, 64 * steps_per_variant);
-        if (rc) return rc;
-        for (int k = 0; k < steps_per_variant; k++) {
+    // Rounds of one step per variant, so that the slow drift of the state
+    // (growth of the block lists) weighs on every variant alike.
+    std::vector<double> t((size_t)nv * 4, 0.0);  // per variant: shears 1..3, all
+    for (int r = 0; r < steps_per_variant; r++)
+        for (int v = 0; v < nv; v++) {
+            for (int s = 0; s < 3; s++) p->D.sweep_variant[s] = v;
+            int rc = vl_profile_start(p, 64);
+            if (rc) return rc;
             if (mode == VL_COALESCED && (rc = vl_fill_ghosts(p))) return rc;
             if ((rc = vl_translate_step(p, dt, mode, nullptr))) return rc;
+            double ms[K_NCLS];
+            int64_t n[K_NCLS];
+            if ((rc = vl_profile_stop(p, ms, n))) return rc;
+            for (int s = 0; s < 3; s++) t[(size_t)v * 4 + s] += ms[K_SHEAR0 + s];
+            t[(size_t)v * 4 + 3] += ms[K_SWEEP];
         }
-        double ms[K_NCLS];
-        int64_t n[K_NCLS];
-        if ((rc = vl_profile_stop(p, ms, n))) return rc;
-        const double per_step = ms[2] / steps_per_variant;  // shear kernels
-        if (ms_out && v < ms_cap) ms_out[v] = per_step;
-        if (v == 0 || per_step < best_ms) {
-            best_ms = per_step;
-            best_v = v;
-        }
+    for (int s = 0; s < 3; s++) {
+        int bv = 0;
+        for (int v = 1; v < nv; v++)
+            if (t[(size_t)v * 4 + s] < t[(size_t)bv * 4 + s]) bv = v;
+        p->D.sweep_variant[s] = bv;
+        best[s] = bv;
     }
-    p->D.sweep_variant = best_v;
-    *best = best_v;
+    if (ms_out)
+        for (int v = 0; v < nv && v < ms_cap; v++) ms_out[v] = t[(size_t)v * 4 + 3] / steps_per_variant;
     return device_status(p);
 }
 

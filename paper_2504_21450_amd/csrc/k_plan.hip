@@ -8,7 +8,10 @@
 //      its upwind face neighbour that moves into it (bit shifts of the
 //      presence masks), allocating slots for the new blocks,
 //   4. emits one work item per block held by an updated cell: its id, its
-//      presence mask and a compacted row of the slots of the cells holding it.
+//      presence mask and a compacted row of the slots of the cells holding it;
+//      in the last shear of a step it also records, per list entry of the
+//      pencil's cells, the item of the entry's block (where the shear leaves
+//      the content flags that the pruning reads).
 // Each cell belongs to exactly one pencil of a shear, so the workgroup owns the
 // lists it grows.  Block ids of a chunk of the union are processed at a time
 // so the LDS footprint is bounded.
@@ -109,6 +112,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     const int64_t base = cell_index(D, co[0], co[1], co[2]);
     const int64_t sd = D.s[pp.d];
     const bool local_pencil = t1 >= H && t1 < H + D.n[pp.e1] && t2 >= H && t2 < H + D.n[pp.e2];
+    const bool last = pp.sidx == 2;  // last shear of the step: record list entry -> item
 
     // 0. cell metadata
     for (int i = tid; i < L; i += 256) {
@@ -288,6 +292,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
             for (int e = 0; e < have; e++) {
                 D.lid[ns + e] = D.lid[s_cs[i] + e];
                 D.lslot[ns + e] = D.lslot[s_cs[i] + e];
+                if (last) __builtin_nontemporal_store(D.litem[s_cs[i] + e], &D.litem[ns + e]);  // entries of earlier chunks
             }
             s_cs[i] = ns;
             s_cap[i] = ncap;
@@ -381,6 +386,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                             const int64_t at = s_cs[i] + s_cnt[i] + lp;
                             D.lid[at] = s_id[k];
                             D.lslot[at] = (int32_t)slot;
+                            if (last) __builtin_nontemporal_store((int32_t)it, &D.litem[at]);
                         } else {
                             atomicOr(&D.ctl->err, (unsigned long long)E_LIST);
                         }
@@ -415,6 +421,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                         for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
                         pos += popc(s_pres[k * WL + iw] & below);
                         D.rows[(int64_t)rb + s_ro[k] + pos] = sls[kk];
+                        if (last) __builtin_nontemporal_store((int32_t)((int64_t)ib + s_ai[k]), &D.litem[at0 + e0 + 64 * kk]);
                     }
                 }
                 // the tail
@@ -428,6 +435,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                     for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
                     pos += popc(s_pres[k * WL + iw] & below);
                     D.rows[(int64_t)rb + s_ro[k] + pos] = D.lslot[cs + e];
+                    if (last) __builtin_nontemporal_store((int32_t)((int64_t)ib + s_ai[k]), &D.litem[cs + e]);
                 }
             }
         }

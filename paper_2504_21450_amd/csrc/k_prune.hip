@@ -1,7 +1,9 @@
 // End-of-step block pruning of the local cells (sparse velocity space,
 // Section 2: blocks are added and removed where necessary).  One workgroup per
 // local cell:
-//   content = blocks with a value >= sparse_min (flag set by the last shear),
+//   content = blocks with a value >= sparse_min: bit t (the cell's place along
+//             the last shear's pencil) of the content-flag words that the last
+//             shear left in its work item of the block (list entry -> item),
 //   keep    = content dilated by the velocity-space buffer (0, 6 or 26
 //             neighbours, clipped to the mesh); keep = all blocks if pruning is
 //             off,
@@ -30,7 +32,7 @@ __device__ inline double block_sum(const Dev &D, int64_t slot, int lane)
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
+__global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, double vol)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_tmp[256];
@@ -53,6 +55,11 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
     const int64_t cs = D.lstart[c];
     const bool prune = D.sparse_min > 0.0;
     const int nbx = D.nblk[0], nby = D.nblk[1], nbz = D.nblk[2];
+    // the cell's word and bit in the last shear's content flags
+    const int tc = H + (last_axis == 0 ? x : last_axis == 1 ? y : z);
+    const uint32_t *fw = D.masks + (tc >> 5);
+    const uint32_t fbit = 1u << (tc & 31);
+    const uint64_t nitems = (uint64_t)min((int64_t)D.ctl->n_items, D.item_cap);
 
     for (int w = tid; w < W; w += 256) {
         s_old[w] = 0u;
@@ -69,7 +76,9 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
             atomicOr(&s_keep[id >> 5], 1u << (id & 31));
             continue;
         }
-        if ((int64_t)slot >= D.lcap || !D.flags[slot]) continue;
+        if ((int64_t)slot >= D.lcap) continue;  // scratch slot of a failed allocation
+        const uint32_t it = (uint32_t)D.litem[cs + e];
+        if ((uint64_t)it >= nitems || !(fw[(int64_t)it * D.wlmax] & fbit)) continue;
         const int bx = id % nbx, by = (id / nbx) % nby, bz = id / (nbx * nby);
         for (int oz = -1; oz <= 1; oz++)
             for (int oy = -1; oy <= 1; oy++)
@@ -248,15 +257,15 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, double vol)
     }
 }
 
-void launch_prune(const Dev &D, int nxt, hipStream_t st)
+void launch_prune(const Dev &D, int nxt, int last_axis, hipStream_t st)
 {
     size_t lds = sizeof(uint32_t) * D.W * 2 + sizeof(int) * (D.W + 1) + 64;
     const double vol = D.dx[0] * D.dx[1] * D.dx[2] * D.dv[0] * D.dv[1] * D.dv[2];
     dim3 g((unsigned)D.nlocal), b(256);
     switch (D.storage) {
-    case VL_F64: hipLaunchKernelGGL(k_prune<VL_F64>, g, b, lds, st, D, nxt, vol); break;
-    case VL_F32: hipLaunchKernelGGL(k_prune<VL_F32>, g, b, lds, st, D, nxt, vol); break;
-    default: hipLaunchKernelGGL(k_prune<VL_BF16>, g, b, lds, st, D, nxt, vol); break;
+    case VL_F64: hipLaunchKernelGGL(k_prune<VL_F64>, g, b, lds, st, D, nxt, last_axis, vol); break;
+    case VL_F32: hipLaunchKernelGGL(k_prune<VL_F32>, g, b, lds, st, D, nxt, last_axis, vol); break;
+    default: hipLaunchKernelGGL(k_prune<VL_BF16>, g, b, lds, st, D, nxt, last_axis, vol); break;
     }
 }
 

@@ -314,7 +314,7 @@ struct VariantInfo {
     int style, pf, minw;
 };
 constexpr VariantInfo VARIANTS[] = {{0, 8, 0}, {0, 8, 6}, {0, 4, 0}, {0, 16, 0}, {1, 8, 0}, {1, 8, 5},
-                                   {2, 8, 0}, {0, 4, 8}, {0, 8, 8}, {2, 8, 8}};
+                                   {2, 8, 0}, {0, 4, 8}, {0, 8, 8}, {2, 8, 8}, {0, 4, 6}};
 constexpr int NVARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 
 template <int ST, int DIR, bool LAST, int V>
@@ -326,6 +326,30 @@ __device__ __forceinline__ void march(const Dev &D, const uint32_t *srow, uint8_
         march_unc<ST, DIR, LAST>(D, srow, sflag, L, c, lane, smin, carry, tb, te);
     else
         march_cond<ST, DIR, LAST, vi.pf>(D, srow, sflag, L, c, lane, smin, carry, tb, te);
+}
+
+// Content flags of the last shear for an item: bit t of word t / 32 tells
+// whether local cell t of the pencil holds the block with a value >=
+// sparse_min after the update.  The words replace the item's presence masks
+// (read at the item's start, not needed after it) in one coalesced store; the
+// pruning finds them through the item recorded for each list entry.
+__device__ __forceinline__ void store_flag_words(const Dev &D, int64_t it, const uint32_t *srow,
+                                                 const uint8_t *sflag, int L, int lane)
+{
+    uint32_t word = 0;
+    for (int t0 = 0; t0 < L; t0 += 64) {
+        const int t = t0 + lane;
+        bool f = false;
+        if (t >= H && t < L - H) {
+            const uint32_t raw = srow[t];
+            f = raw != ABSENT && (raw & ~NEWFLAG) < (uint32_t)D.lcap && sflag[t] != 0;
+        }
+        const unsigned long long b = __ballot(f);
+        const int w = t0 >> 5;
+        if (lane == w) word = (uint32_t)b;
+        if (lane == w + 1) word = (uint32_t)(b >> 32);
+    }
+    if (lane < D.wlmax) D.masks[it * D.wlmax + lane] = word;
 }
 
 // lowest set bit at position >= from of a MAXWL-word mask, or -1
@@ -354,6 +378,7 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
 {
     __shared__ __align__(16) uint32_t s_slot[4][MAXL + 48];
     __shared__ uint8_t s_flag[4][MAXL + 48];
+    __shared__ uint32_t s_seg[4][MAXL / 7 + 2];  // segments of the item: first cell | end << 16
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int d = sp.d, L = sp.L, WL = sp.WL;
@@ -361,6 +386,7 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
     const int64_t nitems = min((int64_t)D.ctl->n_items, D.item_cap);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     uint32_t *srow = s_slot[wv];
+    uint32_t *sseg = s_seg[wv];
     double ledger_acc = 0.0;
 
     for (int64_t it = (int64_t)blockIdx.x * 4 + wv; it < nitems; it += nwaves) {
@@ -414,26 +440,30 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
         // a segment's first cell at least 6 cells read as zero, so the
         // reconstruction state there is the zero state a march starts from;
         // the rounding carry runs on across segments.
-        int tb = first_bit(m, 0);
-        while (tb >= 0) {
+        // The segments are listed in LDS first, so the masks need no
+        // registers during the marches.
+        int nseg = 0;
+        for (int tb = first_bit(m, 0); tb >= 0;) {
             const int g = first_bit(gap, tb + 1);
             const int te = (g >= 0) ? g + 3 : last_bit(m) + 4;
+            if (lane == 0) sseg[nseg] = (uint32_t)tb | ((uint32_t)te << 16);
+            nseg++;
+            tb = (g >= 0) ? first_bit(m, g) : -1;
+        }
+        wave_sync_lds();
+        for (int k = 0; k < nseg; k++) {
+            const uint32_t v = uniform_u32(sseg[k]);
+            const int tb = (int)(v & 0xffffu), te = (int)(v >> 16);
             if (npos == ~0ull)
                 march<ST, 1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
             else if (nneg == ~0ull)
                 march<ST, -1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
             else
                 march<ST, 0, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
-            tb = (g >= 0) ? first_bit(m, g) : -1;
         }
         if constexpr (LAST) {
-            // content flags of the written cells, one store per cell in parallel
             wave_sync_lds();
-            for (int t = 3 + lane; t < L - 3; t += 64) {
-                const uint32_t raw = srow[t];
-                const uint32_t sl = raw & ~NEWFLAG;
-                if (raw != ABSENT && sl < (uint32_t)D.lcap) D.flags[sl] = sflag[t];
-            }
+            store_flag_words(D, it, srow, sflag, L, lane);
         }
 
         if constexpr (ST != VL_F64) {
@@ -637,11 +667,7 @@ __device__ __forceinline__ void sweep_stream(const Dev &D, const SweepParams &sp
             march_stream<ST, 0, LAST>(D, X, Y, sflag, L, c, lane, sp.sparse_min, carry, q, build);
         if constexpr (LAST) {
             wave_sync_lds();
-            for (int t = 3 + lane; t < L - 3; t += 64) {
-                const uint32_t raw = X[t];
-                const uint32_t sl = raw & ~NEWFLAG;
-                if (raw != ABSENT && sl < (uint32_t)D.lcap) D.flags[sl] = sflag[t];
-            }
+            store_flag_words(D, it, X, sflag, L, lane);
         }
         if constexpr (ST != VL_F64) {
             const int p = D.items[it].pencil;
@@ -722,6 +748,7 @@ static void launch_st(const Dev &D, const SweepParams &sp, int v, hipStream_t st
     case 7: launch_variant<ST, LAST, 7>(D, sp, st); break;
     case 8: launch_variant<ST, LAST, 8>(D, sp, st); break;
     case 9: launch_variant<ST, LAST, 9>(D, sp, st); break;
+    case 10: launch_variant<ST, LAST, 10>(D, sp, st); break;
     default: launch_variant<ST, LAST, 0>(D, sp, st); break;
     }
 }
@@ -744,7 +771,7 @@ void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3
     sp.dt = dt;
     sp.sparse_min = D.sparse_min;
     sp.ledger = ledger;
-    const int v = (D.sweep_variant >= 0 && D.sweep_variant < NVARIANTS) ? D.sweep_variant : 0;
+    const int v = (D.sweep_variant[sidx] >= 0 && D.sweep_variant[sidx] < NVARIANTS) ? D.sweep_variant[sidx] : 0;
     switch (D.storage) {
     case VL_F64: last ? launch_st<VL_F64, true>(D, sp, v, st) : launch_st<VL_F64, false>(D, sp, v, st); break;
     case VL_F32: last ? launch_st<VL_F32, true>(D, sp, v, st) : launch_st<VL_F32, false>(D, sp, v, st); break;

@@ -73,16 +73,17 @@ struct Dev {
     void *pool;
     int64_t lcap, gcap, trash;
     int32_t *ring;
-    uint8_t *flags;          // content flag per local slot (set by the last shear)
     int64_t *lstart;
     int32_t *lcount, *lcapa;
     int32_t *lsorted;        // length of the ascending prefix of each list (growth appends after it)
     int32_t *lid, *lslot;
+    int32_t *litem;          // per list entry: the last shear's work item of the block
     int64_t reg_off[3], reg_cap[3];
     int32_t *rows;
     int64_t row_cap;
     Item *items;
-    uint32_t *masks;
+    uint32_t *masks;         // per item: presence along the pencil; after the last
+                             // shear, the content flags of the updated cells
     int64_t item_cap;
     int wlmax;
     Ctl *ctl;
@@ -91,7 +92,7 @@ struct Dev {
     double *cell_red;        // nlocal doubles of per-cell partial sums
     double *red;             // small reduction scratch (>= 1024 doubles)
     int32_t *cell_cnt;       // nlocal ints (export helper)
-    int sweep_variant;       // shear kernel variant (autotuner)
+    int sweep_variant[3];    // shear kernel variant of each shear of the order (autotuner)
 };
 
 __host__ __device__ inline int64_t cell_index(const Dev &D, int x, int y, int z)
@@ -158,7 +159,7 @@ void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3]
 int sweep_variants();
 void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, bool last,
                   double *ledger, hipStream_t st);
-void launch_prune(const Dev &D, int nxt_region, hipStream_t st);
+void launch_prune(const Dev &D, int nxt_region, int last_axis, hipStream_t st);
 void launch_cell_mass(const Dev &D, hipStream_t st);
 void launch_reduce(const Dev &D, const double *in, int64_t n, double *out, hipStream_t st);
 void launch_moments(const Dev &D, double *dn, double *dV, double *dP, hipStream_t st);

@@ -82,6 +82,10 @@ def test_recording_follows_dt_variant_and_courant_changes(sparse_small):
     run_gpu(a, w.dt, 1)
     g.graph_step(w.dt)
     assert same(a, g)
+    g.set_variant((4, 6, 2))  # per-shear choices are part of the recording
+    run_gpu(a, w.dt, 1)
+    g.graph_step(w.dt)
+    assert same(a, g)
     table = np.zeros((3, 4 * max(w.nblk)))
     table[0] = 1.0
     table[1] = -1.0

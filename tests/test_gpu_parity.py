@@ -196,10 +196,38 @@ def test_all_shear_variants_and_autotuner_are_bit_identical(sparse_small):
     assert nvar >= 4
     a = gpu_partition(w)
     best, ms = a.autotune(w.dt, B.VL_COALESCED, steps_per_variant=1)
-    assert 0 <= best < nvar and len(ms) == nvar
+    assert len(best) == 3 and all(0 <= v < nvar for v in best) and len(ms) == nvar
+    assert a.variants() == (best, nvar)
     b = gpu_partition(w)
     run_gpu(b, w.dt, nvar)
     assert all(np.array_equal(x, y) for x, y in zip(a.export(), b.export()))
+
+
+def test_per_shear_variants_mix_bit_identically(sparse_small):
+    """Each shear of the order may run its own variant (the third shear's
+    kernels also record the content flags): mixed choices give the state of
+    one variant bit for bit; out-of-range choices are refused and change
+    nothing."""
+    w = sparse_small
+    print_case("per-shear variants")
+    ref = gpu_partition(w)
+    run_gpu(ref, w.dt, 2)
+    want = ref.export()
+    _, nvar = ref.variants()
+    for vs in [(nvar - 1, 0, 4), (6, nvar - 1, 2), (1, 4, nvar - 1)]:
+        p = gpu_partition(w)
+        p.set_variant(vs)
+        assert p.variants() == (vs, nvar)
+        run_gpu(p, w.dt, 2)
+        assert all(np.array_equal(x, y) for x, y in zip(p.export(), want)), vs
+    p = gpu_partition(w)
+    p.set_variant((2, 3, 4))
+    for bad in [(0, 0, nvar), (-1, 0, 0), (0, 64, 0)]:
+        with pytest.raises(B.VlasovError):
+            p.set_variant(bad)
+        assert p.variants() == ((2, 3, 4), nvar)
+    with pytest.raises(ValueError):
+        p.set_variant((1, 2))
 
 
 @pytest.mark.parametrize("k", [1, 2])

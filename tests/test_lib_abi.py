@@ -105,6 +105,10 @@ def test_null_handles_are_rejected():
     assert lib.vl_fill_ghosts(None) == B.VL_ERR_ARG
     assert lib.vl_translate_step(None, 1.0, 0, None) == B.VL_ERR_ARG
     assert lib.vl_sync(None) == B.VL_ERR_ARG
+    v3 = np.zeros(3, np.int32)
+    assert lib.vl_set_shear_variants(None, B._ptr(v3)) == B.VL_ERR_ARG
+    assert lib.vl_get_shear_variants(None, B._ptr(v3), None) == B.VL_ERR_ARG
+    assert lib.vl_set_variant(None, 0) == B.VL_ERR_ARG
     lib.vl_destroy(None)
 
 
