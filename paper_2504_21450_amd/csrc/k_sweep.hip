@@ -78,6 +78,56 @@ constexpr int PF = 8;  // cells prefetched ahead of the reconstruction front
 
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// max(0, min(x, y)); in FP32 one median-of-three instruction (x >= 0 here,
+// and a zero result takes the sign of the side afterwards, so the sign of a
+// zero makes no difference)
+template <typename C>
+__device__ __forceinline__ C clamp_min0(C x, C y)
+{
+    if constexpr (std::is_same<C, float>::value)
+        return __builtin_amdgcn_fmed3f(0.0f, x, y);
+    else
+        return fmax((C)0, fmin(x, y));
+}
+
+// One block (64 values of one cell) as a buffer resource: the block's address
+// is formed in scalar registers and each lane's value is at byte offset
+// lane * bytes, so no vector instruction computes addresses in the marches.
+// Offsets past the block (none occur) would read zero and drop stores.
+typedef unsigned int vl_u32x2 __attribute__((ext_vector_type(2)));
+constexpr int RSRC_WORD3 = 0x00020000;  // untyped 32-bit buffer access on this architecture
+
+template <int ST>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const Dev &D, uint32_t slot)
+{
+    constexpr int NB = BLK * Storage<ST>::BYTES;
+    return __builtin_amdgcn_make_buffer_rsrc((char *)D.pool + (uint64_t)slot * NB, (short)0, NB, RSRC_WORD3);
+}
+
+template <int ST>
+__device__ __forceinline__ auto block_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    if constexpr (ST == VL_F64)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else if constexpr (ST == VL_F32)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    else
+        return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+
+__device__ __forceinline__ void block_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(vl_u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void block_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void block_store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint16_t v)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
+}
+
 // One (pencil, block) item: march along the pencil.  DIR = +1 when every
 // lane's Courant number is positive, -1 when every one is negative, 0 when
 // the block straddles v = 0 (then the upwind side is chosen per lane).
@@ -161,8 +211,8 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
             // limited face offsets of cell t-2
             const C ai = a2;
             const C dL = ai - face_prev, dR = face - ai;
-            const C mL = fmax((C)0, fmin(fabs(dL), copysign((C)2.0, dL) * dR));
-            const C mR = fmax((C)0, fmin(fabs(dR), copysign((C)2.0, dR) * dL));
+            const C mL = clamp_min0(fabs(dL), copysign((C)2.0, dL) * dR);
+            const C mR = clamp_min0(fabs(dR), copysign((C)2.0, dR) * dL);
             const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
             const double Fc = fma(P, dRp, fma(Q, dLp, c * (double)ai));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
@@ -231,13 +281,7 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
     auto fetch = [&](int t) -> C {
         uint32_t sl = uniform_u32(srow[t]);
         sl = (sl & NEWFLAG) ? zslot : sl;
-        const char *blk = (const char *)D.pool + (uint64_t)sl * (BLK * BS);
-        if constexpr (ST == VL_F64)
-            return *(const double *)(blk + lane_off);
-        else if constexpr (ST == VL_F32)
-            return *(const float *)(blk + lane_off);
-        else
-            return bf16_to_f32(*(const uint16_t *)(blk + lane_off));
+        return block_load<ST>(block_rsrc<ST>(D, sl), lane_off);
     };
 
     C a1 = 0, a2 = 0, a3 = 0;
@@ -261,30 +305,29 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
             const C face = a2 + (C)0.5 * (a1 - a2) - (da - da_prev) * (C)(1.0 / 6.0);
             const C ai = a2;
             const C dL = ai - face_prev, dR = face - ai;
-            const C mL = fmax((C)0, fmin(fabs(dL), copysign((C)2.0, dL) * dR));
-            const C mR = fmax((C)0, fmin(fabs(dR), copysign((C)2.0, dR) * dL));
+            const C mL = clamp_min0(fabs(dL), copysign((C)2.0, dL) * dR);
+            const C mR = clamp_min0(fabs(dR), copysign((C)2.0, dR) * dL);
             const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
             const double Fc = fma(P, dRp, fma(Q, dLp, c * (double)ai));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
             if (t >= 6 && t < L && t < te) {  // past te: the next segment's march
                 const uint32_t sl3 = uniform_u32(srow[t - 3]);
                 if (sl3 != ABSENT) {
-                    const uint32_t s3 = sl3 & ~NEWFLAG;
-                    char *dst = (char *)D.pool + (uint64_t)s3 * (BLK * BS);
+                    const __amdgpu_buffer_rsrc_t dst = block_rsrc<ST>(D, sl3 & ~NEWFLAG);
                     double nv;
                     if constexpr (ST == VL_F64) {
                         nv = (double)a3 + (Ff_prev - Ff);
-                        *(double *)(dst + lane_off) = nv;
+                        block_store(dst, lane_off, nv);
                     } else {
                         const double x = (double)a3 + (Ff_prev - Ff) + carry;
                         if constexpr (ST == VL_F32) {
                             const float q = (float)x;
                             nv = (double)q;
-                            *(float *)(dst + lane_off) = q;
+                            block_store(dst, lane_off, q);
                         } else {
                             const uint16_t h = bf16_rne_f64(x);
                             nv = (double)bf16_to_f32(h);
-                            *(uint16_t *)(dst + lane_off) = h;
+                            block_store(dst, lane_off, h);
                         }
                         carry = x - nv;
                     }
@@ -569,8 +612,8 @@ __device__ __forceinline__ void march_stream(const Dev &D, const uint32_t *X, co
             const C face = a2 + (C)0.5 * dl - (da - da_prev) * (C)(1.0 / 6.0);
             const C ai = a2;
             const C dL = ai - face_prev, dR = face - ai;
-            const C mL = fmax((C)0, fmin(fabs(dL), copysign((C)2.0, dL) * dR));
-            const C mR = fmax((C)0, fmin(fabs(dR), copysign((C)2.0, dR) * dL));
+            const C mL = clamp_min0(fabs(dL), copysign((C)2.0, dL) * dR);
+            const C mR = clamp_min0(fabs(dR), copysign((C)2.0, dR) * dL);
             const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
             const double Fc = fma(P, dRp, fma(Q, dLp, c * (double)ai));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
