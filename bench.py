@@ -60,15 +60,22 @@ def parse_variant(s):
 
 def measured_traffic(storage, variant, workload):
     """HBM bytes per shear launch from the committed rocprofv3 counter runs of
-    the same command, if they were taken on the current kernel source with the
-    same shear variants; else None."""
+    the same command, if they were taken on the current kernel source: the
+    counters give, for each variant profiled, the bytes of the first, second
+    and third shear launch of a step; a step that runs variants (a, b, c)
+    moves the mean of a's first, b's second and c's third.  None if the
+    counters are stale or a variant was not profiled."""
     path = os.path.join(ROOT, "profiles", "shear_traffic_%s.json" % storage)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("workload") != workload:
         return None
-    return d.get("hbm_bytes_per_launch", {}).get(variant_key(variant))
+    by = d.get("hbm_bytes_per_launch_by_shear", {})
+    vs = [int(x) for x in variant_key(variant).split(",")]
+    if not all(str(v) in by for v in vs):
+        return None
+    return sum(by[str(v)][s] for s, v in enumerate(vs)) / 3.0
 
 
 def cpu_baseline(w, sample, min_seconds=10.0, max_steps=40):
