@@ -40,39 +40,6 @@ __device__ inline void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename F>
-struct Recon {
-    // slope of the middle cell of (am, a0, ap)
-    __device__ static F slope(F am, F a0, F ap)
-    {
-        const F dl = a0 - am, dr = ap - a0;
-        const F cen = (F)0.5 * (ap - am);
-        F m = fmin(fabs(cen), (F)2.0 * fabs(dl));
-        m = fmin(m, (F)2.0 * fabs(dr));
-        const F s = cen > (F)0 ? m : -m;
-        return (dl * dr > (F)0) ? s : (F)0;
-    }
-    // limited parabola of cell value a between faces l and r: returns edge
-    // (right face if pos else left face), dA = r - l and a6
-    __device__ static void limit(F a, F l, F r, bool pos, F &edge, F &dA, F &a6)
-    {
-        const bool flat = (r - a) * (a - l) <= (F)0;
-        const F dd = r - l;
-        const F mm = a - (F)0.5 * (l + r);
-        const F dm = dd * mm;
-        const F d26 = dd * dd * (F)(1.0 / 6.0);
-        const bool b1 = dm > d26;
-        const bool b2 = !b1 && (-d26 > dm);
-        F ll = b1 ? (F)3.0 * a - (F)2.0 * r : l;
-        F rr = b2 ? (F)3.0 * a - (F)2.0 * l : r;
-        ll = flat ? a : ll;
-        rr = flat ? a : rr;
-        dA = rr - ll;
-        a6 = (F)6.0 * (a - (F)0.5 * (ll + rr));
-        edge = pos ? rr : ll;
-    }
-};
-
 constexpr uint32_t ABSENT = 0xffffffffu;
 constexpr int PF = 8;  // cells prefetched ahead of the reconstruction front
 
