@@ -126,7 +126,9 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         s_srt[i] = D.lsorted[c];
     }
     for (int w = tid; w < W; w += 256) s_bm[w] = 0u;
+    if (tid == 0) s_base[3] = failed(D) ? 1ull : 0ull;
     __syncthreads();
+    if (s_base[3]) return;  // fail-stop, one decision per workgroup (nothing written yet)
     const int lane = tid & 63, wave = tid >> 6;
 
     // 1. union bitmap: a wavefront reads one cell's sorted list at a time,

@@ -42,6 +42,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
     __shared__ unsigned long long s_base[3];
     __shared__ unsigned long long s_rbase;
     __shared__ int s_cnt[4];
+    __shared__ int s_fail;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int W = D.W;
     uint32_t *s_old = (uint32_t *)smem;
@@ -66,7 +67,9 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
         s_keep[w] = 0u;
     }
     if (tid < 4) s_cnt[tid] = 0;
+    if (tid == 0) s_fail = failed(D) ? 1 : 0;
     __syncthreads();
+    if (s_fail) return;  // fail-stop, one decision per workgroup (nothing written yet)
     // old set and dilated content
     for (int e = tid; e < cnt; e += 256) {
         const int32_t id = D.lid[cs + e];

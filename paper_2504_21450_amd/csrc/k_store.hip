@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_fill(Dev D, SrcTable src, int lo0, int 
     const int lane = threadIdx.x & 63;
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t total = (int64_t)e0 * e1 * e2;
-    if (w >= total) return;
+    if (w >= total || failed(D)) return;  // one wave per cell, no barriers
     const int x = lo0 + (int)(w % e0);
     const int y = lo1 + (int)((w / e0) % e1);
     const int z = lo2 + (int)(w / ((int64_t)e0 * e1));
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_cell_mass(Dev D)
 {
     const int lane = threadIdx.x & 63;
     const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= D.nlocal) return;
+    if (q >= D.nlocal || failed(D)) return;
     int x, y, z;
     local_coords(D, q, x, y, z);
     const int64_t c = cell_index(D, x + H, y + H, z + H);
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void k_moments(Dev D, double *dn, double *dV, 
 {
     const int lane = threadIdx.x & 63;
     const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= D.nlocal) return;
+    if (q >= D.nlocal || failed(D)) return;
     int x, y, z;
     local_coords(D, q, x, y, z);
     const int64_t c = cell_index(D, x + H, y + H, z + H);

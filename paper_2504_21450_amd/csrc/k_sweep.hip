@@ -700,6 +700,7 @@ __device__ __forceinline__ void sweep_stream(const Dev &D, const SweepParams &sp
 template <int ST, bool LAST, int V>
 __global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
 {
+    if (failed(D)) return;  // waves are independent: no barrier to keep
     if constexpr (VARIANTS[V].style == 2)
         sweep_stream<ST, LAST>(D, sp);
     else
@@ -709,6 +710,7 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, SweepParams sp)
 template <int ST, bool LAST, int V, int MINW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW))) void k_sweep_occ(Dev D, SweepParams sp)
 {
+    if (failed(D)) return;
     if constexpr (VARIANTS[V].style == 2)
         sweep_stream<ST, LAST>(D, sp);
     else

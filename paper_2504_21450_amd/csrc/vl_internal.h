@@ -49,10 +49,12 @@ struct Ctl {
     unsigned long long ghost_top, ghost_list_top;
     unsigned long long list_top[2];
     unsigned long long n_items, row_top, work;
-    unsigned long long err;
     unsigned long long upd_ps[3], read_ps[3], items[3];
     unsigned long long cum_upd, cum_read;  // never reset: totals since init
-    unsigned long long pad[6];
+    // error bits on a cache line of their own: every kernel reads them at its
+    // start (fail-stop) while the counters above take atomics
+    alignas(128) unsigned long long err;
+    unsigned long long pad[15];
 };
 
 struct Item {
@@ -94,6 +96,17 @@ struct Dev {
     int32_t *cell_cnt;       // nlocal ints (export helper)
     int sweep_variant[3];    // shear kernel variant of each shear of the order (autotuner)
 };
+
+// Fail-stop: once a capacity error is recorded, every later kernel of the
+// partition returns at once, so a partition whose lists or slots may be
+// inconsistent is never read (the host reports VL_ERR_CAPACITY at its next
+// synchronising call and refuses further work).
+__device__ inline bool failed(const Dev &D)
+{
+    // errors of earlier kernels are visible at launch; one raised by another
+    // workgroup of the same kernel may be missed, which every kernel tolerates
+    return D.ctl->err != 0ull;
+}
 
 __host__ __device__ inline int64_t cell_index(const Dev &D, int x, int y, int z)
 {

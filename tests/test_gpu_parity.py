@@ -174,6 +174,24 @@ def test_capacity_overflow_is_reported():
     assert p.step_rc(1.0, B.VL_PER_SWEEP) == B.VL_ERR_STATE
 
 
+def test_kernels_stop_after_a_capacity_error():
+    """Fail-stop: after the device records an overflow, the steps, graph
+    replays and moments already enqueued do nothing (no kernel reads the
+    inconsistent lists), and the next synchronising call reports the error."""
+    n, nblk = (4, 4, 4), (2, 2, 2)
+    st = random_state(n, nblk, 33, density=0.3)
+    nb = int(st[0][-1])
+    p = B.Partition(n, nblk, (4.0, 5.0, 7.0), (-4.0,) * 3, (1.0,) * 3, *st, block_capacity=nb)
+    print_case("steps after a capacity error")
+    for _ in range(4):
+        assert p.lib.vl_fill_ghosts(p.h) == B.VL_OK
+        assert p.step_rc(1.0, B.VL_COALESCED) == B.VL_OK      # asynchronous: no check yet
+    assert p.lib.vl_graph_step(p.h, 1.0, B.VL_COALESCED, 2) == B.VL_OK
+    p.moments(total=False)                                   # asynchronous as well
+    assert p.lib.vl_sync(p.h) == B.VL_ERR_CAPACITY
+    assert p.lib.vl_sync(p.h) == B.VL_ERR_STATE
+
+
 def test_all_shear_variants_and_autotuner_are_bit_identical(sparse_small):
     """Every compiled shear variant (store scheme, prefetch depth, occupancy)
     gives the same state bit for bit, so the autotuner's real steps leave the
