@@ -37,7 +37,9 @@
  *    and VL_ERR_CFL nothing has been enqueued.  Device-side overflow of a
  *    capacity is recorded on the device and reported as VL_ERR_CAPACITY by
  *    the next call that synchronises; the partition is then invalid and must
- *    be re-initialised with larger capacities.
+ *    be re-initialised with larger capacities.  Work enqueued after the
+ *    overflow (steps, graph replays, ghost updates, moments) does nothing on
+ *    the device: its outputs are not written.
  *  - A handle is not thread-safe; separate handles on separate streams are
  *    independent.
  */
