@@ -28,10 +28,10 @@ def workload(name, n, nblk, st, order=(0, 1, 2), sparse_min=2.5e-10, vbuffer=6):
                       B.VL_F64, order, *st)
 
 
-def both_modes_match_oracle(w, steps=2):
+def both_modes_match_oracle(w, steps=2, **kw):
     want = None
     for mode in (B.VL_COALESCED, B.VL_PER_SWEEP):
-        p = gpu_partition(w)
+        p = gpu_partition(w, **kw)
         run_gpu(p, w.dt, steps, mode)
         got = p.export()
         if want is None:
@@ -96,4 +96,6 @@ def test_largest_velocity_mesh():
     f = rng.uniform(0.0, 1e-9, ids.size * 64)
     w = workload("widest", n, nblk, (off, ids, f))
     print_case("largest velocity mesh")
-    both_modes_match_oracle(w)
+    # dilation around isolated blocks grows the lists about ninefold in the
+    # first step, and the ghost domain of a 3x3x3 box is 26 times the box
+    both_modes_match_oracle(w, slack=16.0)
