@@ -59,8 +59,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError("libvlasov.so not built: run `python -m paper_2504_21450_amd.build` "
-                           "(or __graft_entry__.build())")
+        raise RuntimeError("libvlasov.so not built: run `python -m paper_2504_21450_amd.build`")
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.vl_workspace_bytes.restype = C.c_size_t

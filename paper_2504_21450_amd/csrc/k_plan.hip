@@ -132,17 +132,32 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     const int lane = tid & 63, wave = tid >> 6;
 
     // 1. union bitmap: a wavefront reads one cell's sorted list at a time,
-    //    four coalesced loads per lane in flight
-    for (int i = wave; i < L; i += 4) {
+    //    four coalesced loads per lane, and the first 256 entries of its next
+    //    cell are in flight while it files the current one
+    auto load_ids = [&](int i, int e0, int32_t (&ids)[4]) {
         const int cnt = s_cnt[i];
         const int32_t *lst = D.lid + s_cs[i];
-        for (int e0 = lane; e0 < cnt; e0 += 256) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) ids[k] = (e0 + 64 * k < cnt) ? lst[e0 + 64 * k] : -1;
+    };
+    auto file_ids = [&](const int32_t (&ids)[4]) {
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (ids[k] >= 0) atomicOr(&s_bm[ids[k] >> 5], 1u << (ids[k] & 31));
+    };
+    {
+        int32_t nxt[4] = {-1, -1, -1, -1};
+        if (wave < L) load_ids(wave, lane, nxt);
+        for (int i = wave; i < L; i += 4) {
             int32_t ids[4];
 #pragma unroll
-            for (int k = 0; k < 4; k++) ids[k] = (e0 + 64 * k < cnt) ? lst[e0 + 64 * k] : -1;
-#pragma unroll
-            for (int k = 0; k < 4; k++)
-                if (ids[k] >= 0) atomicOr(&s_bm[ids[k] >> 5], 1u << (ids[k] & 31));
+            for (int k = 0; k < 4; k++) ids[k] = nxt[k];
+            if (i + 4 < L) load_ids(i + 4, lane, nxt);
+            file_ids(ids);
+            for (int e0 = lane + 256; e0 < s_cnt[i]; e0 += 256) {  // lists longer than 256
+                load_ids(i, e0, ids);
+                file_ids(ids);
+            }
         }
     }
     __syncthreads();
@@ -174,22 +189,44 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         // run that starts at s_pos[i] and ends at the first rank beyond the
         // chunk; the entries appended by earlier shears of the step (the
         // tail) are all looked at in every chunk.
+        // The first 256 run entries and the first tail entries of a wavefront's
+        // next cell are loaded while it files the current one.
+        auto load_run = [&](int i, int32_t (&ids)[4], int32_t &tail0) {
+            const int cnt = s_cnt[i], srt = s_srt[i], pos = s_pos[i];
+            const int32_t *lst = D.lid + s_cs[i];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int e = pos + 64 * u + lane;
+                ids[u] = (e < srt) ? lst[e] : -1;
+            }
+            tail0 = (srt + lane < cnt) ? lst[srt + lane] : -1;
+        };
+        int32_t nid[4] = {-1, -1, -1, -1}, ntail = -1;
+        if (wave < L) load_run(wave, nid, ntail);
         for (int i = wave; i < L; i += 4) {
             const int cnt = s_cnt[i], srt = s_srt[i];
             const int32_t *lst = D.lid + s_cs[i];
             const uint32_t cbit = 1u << (i & 31);
             const int cw = i >> 5;
+            int32_t ids[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) ids[u] = nid[u];
+            const int32_t tail0 = ntail;
+            if (i + 4 < L) load_run(i + 4, nid, ntail);
             // 256 entries are loaded at once (the run usually continues) and
             // taken 64 at a time until the first one beyond the chunk
             int pos = s_pos[i];
             bool more = pos < srt;
+            bool first = true;
             while (more) {
-                int32_t ids[4];
+                if (!first) {
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    const int e = pos + 64 * u + lane;
-                    ids[u] = (e < srt) ? lst[e] : -1;
+                    for (int u = 0; u < 4; u++) {
+                        const int e = pos + 64 * u + lane;
+                        ids[u] = (e < srt) ? lst[e] : -1;
+                    }
                 }
+                first = false;
                 int taken = 0;
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
@@ -215,7 +252,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
             }
             if (lane == 0) s_cc[i] = pos - s_pos[i];
             for (int e = srt + lane; e < cnt; e += 64) {
-                const int32_t id = lst[e];
+                const int32_t id = (e == srt + lane) ? tail0 : lst[e];
                 const int w = id >> 5;
                 const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
                 if (k >= 0 && k < rn) {
@@ -399,18 +436,45 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         // rows of the blocks already held: the chunk's run of each list
         // (its place may have moved, its entries have not)
         if (rows_ok) {
+            // the first 256 run entries and the first tail entries of the
+            // wavefront's next cell are loaded while it writes the current one
+            auto load_rows = [&](int i, int32_t (&ids)[4], int32_t (&sls)[4], int32_t &tid0, int32_t &tsl0) {
+                const int64_t at0 = s_cs[i] + s_pos[i];
+                const int n = s_cc[i];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int e = lane + 64 * k;
+                    ids[k] = (e < n) ? D.lid[at0 + e] : -1;
+                    sls[k] = (e < n) ? D.lslot[at0 + e] : 0;
+                }
+                const int64_t te = s_cs[i] + s_srt[i] + lane;
+                const bool has = s_srt[i] + lane < s_cnt[i];
+                tid0 = has ? D.lid[te] : -1;
+                tsl0 = has ? D.lslot[te] : 0;
+            };
+            int32_t nids[4] = {-1, -1, -1, -1}, nsls[4] = {0, 0, 0, 0}, ntid = -1, ntsl = 0;
+            if (wave < L) load_rows(wave, nids, nsls, ntid, ntsl);
             for (int i = wave; i < L; i += 4) {
                 const int64_t at0 = s_cs[i] + s_pos[i];
                 const int n = s_cc[i];
                 const int iw = i >> 5;
                 const uint32_t below = (1u << (i & 31)) - 1u;
-                for (int e0 = lane; e0 < n; e0 += 256) {
-                    int32_t ids[4], sls[4];
+                int32_t ids[4], sls[4];
 #pragma unroll
-                    for (int k = 0; k < 4; k++) {
-                        const int e = e0 + 64 * k;
-                        ids[k] = (e < n) ? D.lid[at0 + e] : -1;
-                        sls[k] = (e < n) ? D.lslot[at0 + e] : 0;
+                for (int k = 0; k < 4; k++) {
+                    ids[k] = nids[k];
+                    sls[k] = nsls[k];
+                }
+                const int32_t tid0 = ntid, tsl0 = ntsl;
+                if (i + 4 < L) load_rows(i + 4, nids, nsls, ntid, ntsl);
+                for (int e0 = lane; e0 < n; e0 += 256) {
+                    if (e0 != lane) {  // lists with more than 256 entries in the chunk
+#pragma unroll
+                        for (int k = 0; k < 4; k++) {
+                            const int e = e0 + 64 * k;
+                            ids[k] = (e < n) ? D.lid[at0 + e] : -1;
+                            sls[k] = (e < n) ? D.lslot[at0 + e] : 0;
+                        }
                     }
 #pragma unroll
                     for (int kk = 0; kk < 4; kk++) {
@@ -429,14 +493,15 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                 // the tail
                 const int64_t cs = s_cs[i];
                 for (int e = s_srt[i] + lane; e < s_cnt[i]; e += 64) {
-                    const int32_t id = D.lid[cs + e];
+                    const bool pre = e == s_srt[i] + lane;
+                    const int32_t id = pre ? tid0 : D.lid[cs + e];
                     const int w = id >> 5;
                     const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
                     if (k < 0 || k >= rn || s_ai[k + 1] == s_ai[k]) continue;
                     int pos = 0;
                     for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
                     pos += popc(s_pres[k * WL + iw] & below);
-                    D.rows[(int64_t)rb + s_ro[k] + pos] = D.lslot[cs + e];
+                    D.rows[(int64_t)rb + s_ro[k] + pos] = pre ? tsl0 : D.lslot[cs + e];
                     if (last) __builtin_nontemporal_store((int32_t)((int64_t)ib + s_ai[k]), &D.litem[cs + e]);
                 }
             }
