@@ -93,6 +93,8 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     int *s_pos = (int *)q; q += sizeof(int) * MAXL;   // first list entry of the current chunk
     int *s_cc = (int *)q; q += sizeof(int) * MAXL;    // list entries in the current chunk
     int *s_srt = (int *)q; q += sizeof(int) * MAXL;   // ascending prefix length of each list
+    int64_t *s_mvsrc = (int64_t *)q; q += sizeof(int64_t) * MAXL;  // list moved: its old place
+    int *s_mvn = (int *)q; q += sizeof(int) * MAXL;   // list moved: entries to copy
     uint32_t *s_bm = (uint32_t *)q; q += sizeof(uint32_t) * W;
     int *s_rank = (int *)q; q += sizeof(int) * (W + 1);
     uint32_t *s_pres = (uint32_t *)q; q += sizeof(uint32_t) * R * WL;
@@ -312,8 +314,11 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         }
         __syncthreads();
         // a cell whose list cannot take this chunk's new blocks moves its
-        // list to a larger place at the end of its list region
+        // list to a larger place at the end of its list region: the places
+        // are taken per cell, then each wavefront copies the lists of its
+        // cells (coalesced; the old places are not reused within the step)
         for (int i = tid; i < L; i += 256) {
+            s_mvn[i] = 0;
             const int req = s_req[i];
             if (req == 0) continue;
             s_req[i] = 0;
@@ -328,16 +333,24 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                 continue;
             }
             const int64_t ns = D.reg_off[reg] + (int64_t)nb0;
-            for (int e = 0; e < have; e++) {
-                D.lid[ns + e] = D.lid[s_cs[i] + e];
-                D.lslot[ns + e] = D.lslot[s_cs[i] + e];
-                if (last) __builtin_nontemporal_store(D.litem[s_cs[i] + e], &D.litem[ns + e]);  // entries of earlier chunks
-            }
+            s_mvsrc[i] = s_cs[i];
+            s_mvn[i] = have;
             s_cs[i] = ns;
             s_cap[i] = ncap;
             const int64_t c = base + sd * i;
             D.lstart[c] = ns;
             D.lcapa[c] = ncap;
+        }
+        __syncthreads();
+        for (int i = wave; i < L; i += 4) {
+            const int n = s_mvn[i];
+            if (n == 0) continue;
+            const int64_t from = s_mvsrc[i], to = s_cs[i];
+            for (int e = lane; e < n; e += 64) {
+                D.lid[to + e] = D.lid[from + e];
+                D.lslot[to + e] = D.lslot[from + e];
+                if (last) D.litem[to + e] = D.litem[from + e];  // entries of earlier chunks
+            }
         }
         __syncthreads();
         const int nact = block_scan_excl(s_ai, rn, s_tmp);
@@ -530,7 +543,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
 
 size_t plan_lds_bytes(int W, int R, int WL)
 {
-    size_t b = sizeof(int64_t) * MAXL + sizeof(int) * MAXL * 7;
+    size_t b = sizeof(int64_t) * MAXL * 2 + sizeof(int) * MAXL * 8;
     b += sizeof(uint32_t) * W + sizeof(int) * (W + 1);
     b += (size_t)R * WL * 4 * 2 + (size_t)R * 4 + (size_t)(R + 1) * 4 * 3;
     return b + 64;
