@@ -24,11 +24,9 @@ constexpr int PR_QUEUE = 512;    // removed / created blocks queued for the wave
 __device__ inline int popc32(uint32_t v) { return __popc(v); }
 
 template <int ST>
-__device__ inline double block_sum(const Dev &D, int64_t slot, int lane)
+__device__ inline double lane_value(const Dev &D, int32_t slot, int lane)
 {
-    double v = Storage<ST>::load(D.pool, slot * BLK + lane);
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return Storage<ST>::load(D.pool, (int64_t)slot * BLK + lane);
 }
 
 template <int ST>
@@ -154,7 +152,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
     }
     const int64_t ns = D.reg_off[nxt] + (int64_t)s_base[0];
     const bool ring_failed = (s_base[2] & 2) != 0;
-    double wmass = 0.0;
+    double lmass = 0.0;  // this lane's share of the removed blocks of this wavefront
 
     // old entries: kept ones move to their sorted position, removed ones are
     // queued (slot) for the mass sum and returned to the ring
@@ -210,12 +208,20 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
             __syncthreads();
         }
         const int nq = min(s_cnt[2], PR_QUEUE);
-        for (int k = wv; k < nq; k += 4) wmass += block_sum<ST>(D, s_q[k], lane);
+        // removed mass: per lane over the wavefront's blocks, four loads in
+        // flight, reduced across the lanes once at the end
+        int k = wv;
+        for (; k + 12 < nq; k += 16) {
+            const double a0 = lane_value<ST>(D, s_q[k], lane), a1 = lane_value<ST>(D, s_q[k + 4], lane);
+            const double a2 = lane_value<ST>(D, s_q[k + 8], lane), a3 = lane_value<ST>(D, s_q[k + 12], lane);
+            lmass += (a0 + a1) + (a2 + a3);
+        }
+        for (; k < nq; k += 4) lmass += lane_value<ST>(D, s_q[k], lane);
         if (s_cnt[2] > PR_QUEUE) {
             // overflow of the queue: sum the rest entry by entry
             for (int e = wv; e < m; e += 4) {
                 const int32_t sl = s_eslot[e];
-                if (sl < 0) wmass += block_sum<ST>(D, (int64_t)(-1 - sl), lane);
+                if (sl < 0) lmass += lane_value<ST>(D, -1 - sl, lane);
             }
         }
         __syncthreads();
@@ -249,6 +255,8 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
         const int nq = min(s_cnt[3], PR_QUEUE);
         for (int k = wv; k < nq; k += 4) Storage<ST>::store(D.pool, (int64_t)s_q[k] * BLK + lane, 0.0);
     }
+    double wmass = lmass;
+    for (int o = 32; o > 0; o >>= 1) wmass += __shfl_xor(wmass, o);
     if (lane == 0) s_wmass[wv] = wmass;
     __syncthreads();
     if (tid == 0) {
