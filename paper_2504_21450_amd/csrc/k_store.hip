@@ -98,21 +98,23 @@ __global__ __launch_bounds__(256) void k_fill(Dev D, SrcTable src, int lo0, int 
 {
     using SW = typename Storage<ST>::Word;
     constexpr int WPB = Storage<ST>::WORDS_PER_BLOCK;  // words per block (<= 64)
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    __shared__ unsigned long long s_need[4][2], s_wgbase[2];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * 4 + wv;
     const int64_t total = (int64_t)e0 * e1 * e2;
-    if (w >= total || failed(D)) return;  // one wave per cell, no barriers
+    // one wave per cell; every wave reaches the workgroup's two barriers
     const int x = lo0 + (int)(w % e0);
     const int y = lo1 + (int)((w / e0) % e1);
     const int z = lo2 + (int)(w / ((int64_t)e0 * e1));
-    if (is_local(D, x, y, z)) return;
+    const bool active = w < total && !failed(D) && !is_local(D, x, y, z);
     const int64_t c = cell_index(D, x, y, z);
     // source cell: the periodic image in this partition, or the cell of the
     // neighbouring partition that holds this position (all local boxes equal,
     // each at least 3 cells wide, so the neighbour is one box away)
-    int64_t s;
-    SrcPart sp;
-    if (!src.remote) {
+    int64_t s = 0;
+    SrcPart sp = src.part[13];
+    if (!active) {
+    } else if (!src.remote) {
         s = cell_index(D, wrap_coord(x, D.n[0]), wrap_coord(y, D.n[1]), wrap_coord(z, D.n[2]));
         sp = src.part[13];
     } else {
@@ -127,16 +129,28 @@ __global__ __launch_bounds__(256) void k_fill(Dev D, SrcTable src, int lo0, int 
         s = cell_index(D, l[0], l[1], l[2]);
         sp = src.part[q];
     }
-    const int cnt = sp.lcount[s];
-    const int64_t ss = sp.lstart[s];
+    const int cnt = active ? sp.lcount[s] : 0;
+    const int64_t ss = active ? sp.lstart[s] : 0;
     const int cap = cnt + cnt / 4 + 32;
-    unsigned long long lb = 0, sb = 0;
+    // list and slot space: one pair of counter updates per workgroup
     if (lane == 0) {
-        lb = atomicAdd(&D.ctl->ghost_list_top, (unsigned long long)cap);
-        sb = atomicAdd(&D.ctl->ghost_top, (unsigned long long)cnt);
+        s_need[wv][0] = active ? (unsigned long long)cap : 0ull;
+        s_need[wv][1] = active ? (unsigned long long)cnt : 0ull;
     }
-    lb = __shfl(lb, 0);
-    sb = __shfl(sb, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long nl = s_need[0][0] + s_need[1][0] + s_need[2][0] + s_need[3][0];
+        const unsigned long long ns = s_need[0][1] + s_need[1][1] + s_need[2][1] + s_need[3][1];
+        s_wgbase[0] = nl ? atomicAdd(&D.ctl->ghost_list_top, nl) : 0ull;
+        s_wgbase[1] = ns ? atomicAdd(&D.ctl->ghost_top, ns) : 0ull;
+    }
+    __syncthreads();
+    if (!active) return;
+    unsigned long long lb = s_wgbase[0], sb = s_wgbase[1];
+    for (int j = 0; j < wv; j++) {
+        lb += s_need[j][0];
+        sb += s_need[j][1];
+    }
     const bool lok = (int64_t)(lb + cap) <= D.reg_cap[2];
     const bool sok = (int64_t)(sb + cnt) <= D.gcap;
     if (!lok || !sok) {
