@@ -1,5 +1,5 @@
 // End-of-step block pruning of the local cells (sparse velocity space,
-// Section 2: blocks are added and removed where necessary).  One workgroup per
+// Section 2: the velocity space gains and loses blocks as needed).  One workgroup per
 // local cell:
 //   content = blocks with a value >= sparse_min: bit t (the cell's place along
 //             the last shear's pencil) of the content-flag words that the last
