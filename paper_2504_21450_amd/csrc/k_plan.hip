@@ -32,6 +32,9 @@ struct PlanParams {
 
 __device__ inline int popc(uint32_t v) { return __popc(v); }
 
+// cells of a pencil rounded up to a multiple of 8 (LDS array length)
+__host__ __device__ inline int plan_cells(int L) { return (L + 7) & ~7; }
+
 // exclusive scan of a[0..n) in place (LDS) by 256 threads; returns the total
 __device__ int block_scan_excl(int *a, int n, int *s_tmp)
 {
@@ -83,18 +86,19 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     const int tid = threadIdx.x;
     const int L = pp.L, WL = pp.WL, W = D.W, R = pp.R;
 
-    // dynamic LDS carve
+    // dynamic LDS carve (per-cell arrays sized by the pencil, a multiple of 8)
+    const int LP = plan_cells(L);
     unsigned char *q = smem;
-    int64_t *s_cs = (int64_t *)q; q += sizeof(int64_t) * MAXL;
-    int *s_cnt = (int *)q; q += sizeof(int) * MAXL;
-    int *s_cap = (int *)q; q += sizeof(int) * MAXL;
-    int *s_new = (int *)q; q += sizeof(int) * MAXL;
-    int *s_req = (int *)q; q += sizeof(int) * MAXL;   // new blocks of this chunk per cell
-    int *s_pos = (int *)q; q += sizeof(int) * MAXL;   // first list entry of the current chunk
-    int *s_cc = (int *)q; q += sizeof(int) * MAXL;    // list entries in the current chunk
-    int *s_srt = (int *)q; q += sizeof(int) * MAXL;   // ascending prefix length of each list
-    int64_t *s_mvsrc = (int64_t *)q; q += sizeof(int64_t) * MAXL;  // list moved: its old place
-    int *s_mvn = (int *)q; q += sizeof(int) * MAXL;   // list moved: entries to copy
+    int64_t *s_cs = (int64_t *)q; q += sizeof(int64_t) * LP;
+    int64_t *s_mvsrc = (int64_t *)q; q += sizeof(int64_t) * LP;  // list moved: its old place
+    int *s_cnt = (int *)q; q += sizeof(int) * LP;
+    int *s_cap = (int *)q; q += sizeof(int) * LP;
+    int *s_new = (int *)q; q += sizeof(int) * LP;
+    int *s_req = (int *)q; q += sizeof(int) * LP;   // new blocks of this chunk per cell
+    int *s_pos = (int *)q; q += sizeof(int) * LP;   // first list entry of the current chunk
+    int *s_cc = (int *)q; q += sizeof(int) * LP;    // list entries in the current chunk
+    int *s_srt = (int *)q; q += sizeof(int) * LP;   // ascending prefix length of each list
+    int *s_mvn = (int *)q; q += sizeof(int) * LP;   // list moved: entries to copy
     uint32_t *s_bm = (uint32_t *)q; q += sizeof(uint32_t) * W;
     int *s_rank = (int *)q; q += sizeof(int) * (W + 1);
     uint32_t *s_pres = (uint32_t *)q; q += sizeof(uint32_t) * R * WL;
@@ -541,9 +545,10 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     }
 }
 
-size_t plan_lds_bytes(int W, int R, int WL)
+size_t plan_lds_bytes(int W, int R, int WL, int L)
 {
-    size_t b = sizeof(int64_t) * MAXL * 2 + sizeof(int) * MAXL * 8;
+    const size_t lp = (size_t)plan_cells(L);
+    size_t b = sizeof(int64_t) * lp * 2 + sizeof(int) * lp * 8;
     b += sizeof(uint32_t) * W + sizeof(int) * (W + 1);
     b += (size_t)R * WL * 4 * 2 + (size_t)R * 4 + (size_t)(R + 1) * 4 * 3;
     return b + 64;
@@ -570,12 +575,12 @@ void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3]
     // chunk size: keep the workgroup's LDS at <= 34 KiB (plus ~3 KiB static),
     // so four planner workgroups fit a compute unit's 160 KiB
     const size_t budget = 34 * 1024;
-    size_t fixed = plan_lds_bytes(D.W, 0, pp.WL);
+    size_t fixed = plan_lds_bytes(D.W, 0, pp.WL, pp.L);
     size_t per = (size_t)pp.WL * 8 + 16;
     int R = (fixed < budget) ? (int)((budget - fixed) / per) : 64;
     if (R < 64) R = 64;
     pp.R = R;
-    size_t lds = plan_lds_bytes(D.W, R, pp.WL);
+    size_t lds = plan_lds_bytes(D.W, R, pp.WL, pp.L);
     int64_t np = (int64_t)pp.n1 * pp.n2;
     if (np <= 0) return;
     hipLaunchKernelGGL(k_plan, dim3((unsigned)np), dim3(256), lds, st, D, pp);
