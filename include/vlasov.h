@@ -247,18 +247,19 @@ int vl_profile_start(vl_partition *p, int32_t max_launches);
 int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches);
 
 /* Autotuner (Section 2.1's shear, kernel shapes only): runs steps_per_variant
- * rounds of real translation steps (each with its ghost update in
- * VL_COALESCED mode), one step with every compiled variant of the shear kernel
- * (store scheme, prefetch depth, occupancy target) per round, times each
- * shear launch with HIP events on the
- * partition's stream, and keeps for each of the three shears of the order
- * the variant that was fastest on it (the third shear, which also records
- * the blocks' content flags, has kernels of its own with other register
- * needs).  All variants compute bit-identical results, so the state advances
- * exactly as with ordinary steps.  best[3] receives the chosen variant of the
- * first, second and third shear; ms_out (optional, ms_cap entries) the
- * milliseconds per step of all three shears with each variant.
- * Synchronises.  Errors as vl_translate_step. */
+ * x (number of compiled variants) real translation steps (each with its ghost
+ * update in VL_COALESCED mode): first one step with every variant of the
+ * shear kernel (store scheme, prefetch depth, occupancy target), then rounds
+ * over the variants within 25 % of the best mean time on some shear, until
+ * the steps are spent.  Each shear launch is timed with HIP events on the
+ * partition's stream; for each of the three shears of the order the variant
+ * with the lowest mean time on it is kept (the third shear, which also
+ * records the blocks' content flags, has kernels of its own with other
+ * register needs).  All variants compute bit-identical results, so the state
+ * advances exactly as with ordinary steps.  best[3] receives the chosen
+ * variant of the first, second and third shear; ms_out (optional, ms_cap
+ * entries) the mean milliseconds per step of all three shears with each
+ * variant.  Synchronises.  Errors as vl_translate_step. */
 int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_variant, int32_t best[3],
                 double *ms_out, int32_t ms_cap);
 

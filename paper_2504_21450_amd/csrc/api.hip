@@ -780,31 +780,53 @@ int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_vari
     if (!p || steps_per_variant < 1 || !best) return VL_ERR_ARG;
     if (p->bad) return VL_ERR_STATE;
     const int nv = sweep_variants();
-    // Rounds of one step per variant, so that the slow drift of the state
-    // (growth of the block lists) weighs on every variant alike.
-    std::vector<double> t((size_t)nv * 4, 0.0);  // per variant: shears 1..3, all
-    for (int r = 0; r < steps_per_variant; r++)
-        for (int v = 0; v < nv; v++) {
-            for (int s = 0; s < 3; s++) p->D.sweep_variant[s] = v;
-            int rc = vl_profile_start(p, 64);
-            if (rc) return rc;
-            if (mode == VL_COALESCED && (rc = vl_fill_ghosts(p))) return rc;
-            if ((rc = vl_translate_step(p, dt, mode, nullptr))) return rc;
-            double ms[K_NCLS];
-            int64_t n[K_NCLS];
-            if ((rc = vl_profile_stop(p, ms, n))) return rc;
-            for (int s = 0; s < 3; s++) t[(size_t)v * 4 + s] += ms[K_SHEAR0 + s];
-            t[(size_t)v * 4 + 3] += ms[K_SWEEP];
+    const int budget = steps_per_variant * nv;      // real steps in all
+    std::vector<double> t((size_t)nv * 4, 0.0);     // per variant: summed ms of shears 1..3, all
+    std::vector<int> k((size_t)nv, 0);              // steps run with each variant
+    auto run = [&](int v) -> int {
+        for (int s = 0; s < 3; s++) p->D.sweep_variant[s] = v;
+        int rc = vl_profile_start(p, 64);
+        if (rc) return rc;
+        if (mode == VL_COALESCED && (rc = vl_fill_ghosts(p))) return rc;
+        if ((rc = vl_translate_step(p, dt, mode, nullptr))) return rc;
+        double ms[K_NCLS];
+        int64_t n[K_NCLS];
+        if ((rc = vl_profile_stop(p, ms, n))) return rc;
+        for (int s = 0; s < 3; s++) t[(size_t)v * 4 + s] += ms[K_SHEAR0 + s];
+        t[(size_t)v * 4 + 3] += ms[K_SWEEP];
+        k[v]++;
+        return VL_OK;
+    };
+    auto mean = [&](int v, int s) { return t[(size_t)v * 4 + s] / k[v]; };
+    // One step with every variant, then rounds over the variants within 25 %
+    // of the best mean on some shear until the steps are spent; rounds keep
+    // the slow growth of the state weighing on the compared variants alike.
+    int done = 0, rc;
+    for (int v = 0; v < nv; v++, done++)
+        if ((rc = run(v))) return rc;
+    while (done < budget) {
+        double bm[3];
+        for (int s = 0; s < 3; s++) {
+            bm[s] = mean(0, s);
+            for (int v = 1; v < nv; v++) bm[s] = std::min(bm[s], mean(v, s));
         }
+        for (int v = 0; v < nv && done < budget; v++) {
+            bool live = false;
+            for (int s = 0; s < 3; s++) live = live || mean(v, s) <= 1.25 * bm[s];
+            if (!live) continue;
+            if ((rc = run(v))) return rc;
+            done++;
+        }
+    }
     for (int s = 0; s < 3; s++) {
         int bv = 0;
         for (int v = 1; v < nv; v++)
-            if (t[(size_t)v * 4 + s] < t[(size_t)bv * 4 + s]) bv = v;
+            if (mean(v, s) < mean(bv, s)) bv = v;
         p->D.sweep_variant[s] = bv;
         best[s] = bv;
     }
     if (ms_out)
-        for (int v = 0; v < nv && v < ms_cap; v++) ms_out[v] = t[(size_t)v * 4 + 3] / steps_per_variant;
+        for (int v = 0; v < nv && v < ms_cap; v++) ms_out[v] = t[(size_t)v * 4 + 3] / k[v];
     return device_status(p);
 }
 

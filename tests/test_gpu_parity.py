@@ -219,6 +219,14 @@ def test_all_shear_variants_and_autotuner_are_bit_identical(sparse_small):
     b = gpu_partition(w)
     run_gpu(b, w.dt, nvar)
     assert all(np.array_equal(x, y) for x, y in zip(a.export(), b.export()))
+    # two steps per variant: a first round over all, then rounds over the
+    # variants near the best; the same number of steps in all
+    a = gpu_partition(w)
+    best, ms = a.autotune(w.dt, B.VL_COALESCED, steps_per_variant=2)
+    assert all(0 <= v < nvar for v in best) and len(ms) == nvar and min(ms) > 0
+    b = gpu_partition(w)
+    run_gpu(b, w.dt, 2 * nvar)
+    assert all(np.array_equal(x, y) for x, y in zip(a.export(), b.export()))
 
 
 def test_per_shear_variants_mix_bit_identically(sparse_small):
