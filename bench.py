@@ -179,8 +179,10 @@ def main():
         from paper_2504_21450_amd import devsample
         if args.autotune:
             # tune on a smaller partition of the same mixture, so that the
-            # measured partition starts its timed steps near its initial state
-            proxy_n = tuple(min(v, c) for v, c in zip(n, (32, 32, 16)))
+            # measured partition starts its timed steps near its initial state;
+            # it keeps the z extent (the z pencils' length decides the last
+            # shear's variant) and at most 32 cells along x and y
+            proxy_n = (min(n[0], 32), min(n[1], 32), n[2])
             wp = W.blob_mixture(n=proxy_n, hot_fraction=args.hot, sample=False,
                                 storage=STORAGES[args.storage])
             pp = devsample.sample_partition(wp, slack=4.0)
