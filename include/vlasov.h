@@ -248,7 +248,9 @@ int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches);
 
 /* Autotuner (Section 2.1's shear, kernel shapes only): runs steps_per_variant
  * x (number of compiled variants) real translation steps (each with its ghost
- * update in VL_COALESCED mode): first one step with every variant of the
+ * update in VL_COALESCED mode, taken as vl_graph_step takes it: from the
+ * sources of the last vl_fill_ghosts_from if there was one, which must exist
+ * when desc.edges is set, else from periodic images): first one step with every variant of the
  * shear kernel (store scheme, prefetch depth, occupancy target), then rounds
  * over the variants within 25 % of the best mean time on some shear, until
  * the steps are spent.  Each shear launch is timed with HIP events on the
@@ -259,7 +261,8 @@ int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches);
  * advances exactly as with ordinary steps.  best[3] receives the chosen
  * variant of the first, second and third shear; ms_out (optional, ms_cap
  * entries) the mean milliseconds per step of all three shears with each
- * variant.  Synchronises.  Errors as vl_translate_step. */
+ * variant.  Synchronises.  Errors as vl_translate_step (VL_ERR_STALE_GHOSTS
+ * when desc.edges is set and no sources were given). */
 int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_variant, int32_t best[3],
                 double *ms_out, int32_t ms_cap);
 

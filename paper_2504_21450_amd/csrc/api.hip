@@ -779,6 +779,10 @@ int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_vari
 {
     if (!p || steps_per_variant < 1 || !best) return VL_ERR_ARG;
     if (p->bad) return VL_ERR_STATE;
+    if (mode != VL_COALESCED && mode != VL_PER_SWEEP) return VL_ERR_ARG;
+    if (!(dt > 0.0) || !isfinite(dt)) return VL_ERR_ARG;
+    if (check_cfl(p, dt)) return VL_ERR_CFL;
+    if (p->desc.edges && !p->has_src) return VL_ERR_STALE_GHOSTS;  // boundary cells need their sources
     const int nv = sweep_variants();
     const int budget = steps_per_variant * nv;      // real steps in all
     std::vector<double> t((size_t)nv * 4, 0.0);     // per variant: summed ms of shears 1..3, all
@@ -787,7 +791,13 @@ int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_vari
         for (int s = 0; s < 3; s++) p->D.sweep_variant[s] = v;
         int rc = vl_profile_start(p, 64);
         if (rc) return rc;
-        if (mode == VL_COALESCED && (rc = vl_fill_ghosts(p))) return rc;
+        if (mode == VL_COALESCED) {
+            // the ghost update a real step would take: from the sources of the
+            // last vl_fill_ghosts_from if there was one, else periodic images
+            enqueue_fill(p, p->stream);
+            VL_HIP(hipGetLastError());
+            p->ghosts_valid = true;
+        }
         if ((rc = vl_translate_step(p, dt, mode, nullptr))) return rc;
         double ms[K_NCLS];
         int64_t n[K_NCLS];

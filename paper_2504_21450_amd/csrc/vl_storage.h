@@ -2,9 +2,10 @@
 //   VL_F64 : double
 //   VL_F32 : float, round to nearest even from FP64
 //   VL_BF16: bfloat16 (upper half of an IEEE float), round to nearest even
-//            from FP64, done as FP64 -> FP32 rounded to odd -> BF16 to nearest
-//            even, which equals one correct rounding because FP32 carries more
-//            than two extra bits beyond BF16's precision.
+//            from FP64 (bf16_rne_f64): FP64 -> FP32 to nearest, with the FP32
+//            word moved one unit toward the FP64 value where it landed exactly
+//            on a BF16 midpoint without being the value, then BF16 to nearest
+//            even.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,17 +28,6 @@ __host__ __device__ inline float bits_f32(uint32_t u)
     float f;
     memcpy(&f, &u, 4);
     return f;
-}
-
-// FP64 -> FP32 rounded to odd (sticky bit in the last place)
-__device__ inline float d2f_odd(double d)
-{
-    float t = __double2float_rz(d);
-    if ((double)t != d) {
-        uint32_t u = f32_bits(t) | 1u;
-        t = bits_f32(u);
-    }
-    return t;
 }
 
 __host__ __device__ inline uint16_t f32_to_bf16_rne(float f)

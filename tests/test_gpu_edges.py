@@ -85,3 +85,21 @@ def test_edge_graph_replays_equal_ordinary_steps(states):
         a.step(1.0, B.VL_COALESCED)
         g.graph_step(1.0, B.VL_COALESCED)
         assert all(np.array_equal(x, y) for x, y in zip(a.export(), g.export())), k
+
+
+def test_autotune_at_a_simulation_edge_equals_ordinary_steps(states):
+    """The autotuner needs the boundary cells' sources and then steps exactly
+    as ordinary steps with those sources do."""
+    st, lo_st, hi_st = states
+    lo, hi = part(lo_st, 0), part(hi_st, 0)
+    a = part(st, EDGES_X)
+    b = part(st, EDGES_X)
+    best = np.zeros(3, np.int32)
+    assert a.lib.vl_autotune(a.h, 1.0, B.VL_COALESCED, 1, best.ctypes.data, None, 0) == B.VL_ERR_STALE_GHOSTS
+    a.fill_ghosts_from(table(a, lo, hi))
+    a.step(1.0, B.VL_COALESCED)
+    _, ms = a.autotune(1.0, B.VL_COALESCED, steps_per_variant=1)
+    for _ in range(1 + len(ms)):
+        b.fill_ghosts_from(table(b, lo, hi))
+        b.step(1.0, B.VL_COALESCED)
+    assert all(np.array_equal(x, y) for x, y in zip(a.export(), b.export()))

@@ -7,7 +7,7 @@ import pytest
 
 from paper_2504_21450_amd import binding as B
 from paper_2504_21450_amd import workloads as W
-from gpuhelp import gpu_partition, need_gpu, print_case
+from gpuhelp import compare_states, gpu_partition, need_gpu, print_case, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -64,10 +64,14 @@ def test_split_partitions_equal_single_partition_bitwise(gt_level):
             p.fill_ghosts_from(neighbours(parts, grid, key))
         for p, _ in parts.values():
             p.step(w.dt, B.VL_COALESCED)
+    o, _ = run_oracle(w, 3)
+    oo, oi, of = o.export_local()
     for key, (p, cells) in parts.items():
         got = p.export()
         want = single.export_cells(cells)
         assert all(np.array_equal(a, b) for a, b in zip(got, want)), key
+        # and against the oracle's periodic whole box: lists exact, values to 1e-12
+        compare_states(got, W.take_cells(oo, oi, of, cells), 1e-12)
 
 
 def test_fill_from_checks_its_neighbours():
@@ -85,3 +89,26 @@ def test_fill_from_checks_its_neighbours():
     p.fill_ghosts_from(nb)
     p.step(w.dt)
     p.sync()
+
+
+def test_autotune_on_a_split_partition_equals_ordinary_steps():
+    """The autotuner's real steps take their ghost update from the stored
+    neighbour sources, as an ordinary step after vl_fill_ghosts_from does (the
+    neighbours stay where they are in both runs)."""
+    w = W.maxwellian_sparse(n=(8, 6, 8), threads=8)
+    grid = (2, 2, 2)
+    print_case("autotune on one partition of a 2x2x2 split")
+    a_parts = split(w, grid)
+    b_parts = split(w, grid)
+    key = (1, 0, 1)
+    a = a_parts[key][0]
+    b = b_parts[key][0]
+    a.fill_ghosts_from(neighbours(a_parts, grid, key))
+    a.step(w.dt, B.VL_COALESCED)
+    best, ms = a.autotune(w.dt, B.VL_COALESCED, steps_per_variant=1)
+    nvar = len(ms)
+    nb = neighbours(b_parts, grid, key)
+    for _ in range(1 + nvar):
+        b.fill_ghosts_from(nb)
+        b.step(w.dt, B.VL_COALESCED)
+    assert all(np.array_equal(x, y) for x, y in zip(a.export(), b.export()))

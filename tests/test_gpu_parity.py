@@ -1,6 +1,8 @@
 """Parity of the HIP translation path (through the C ABI) with the FP64
 oracle: values within 1e-12 relative max-norm, block lists bit-exact, the two
 ghost schemes bit-identical, and the error paths."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -295,3 +297,38 @@ def test_long_pencils_with_gaps_match_oracle_for_every_variant():
         compare_states(p.export(), want, TOL64)
         for x in s:
             assert abs(x["mass_after"] + x["pruned_mass"] - x["mass_before"]) <= 1e-12 * x["mass_before"], v
+
+
+@pytest.mark.parametrize("order", [(0, 1, 2), (2, 0, 1)])
+def test_26_neighbour_velocity_buffer_matches_oracle(sparse_small, order):
+    """Pruning with all 26 velocity-space neighbours kept around the content
+    blocks: values within 1e-12, lists exact, the same block counts, updated
+    cells and pruned mass as the oracle."""
+    w = dataclasses.replace(sparse_small, vbuffer=26, order=order)
+    print_case("26-neighbour buffer, order %s" % (order,))
+    p = gpu_partition(w)
+    gs = run_gpu(p, w.dt, 3, stats=True)
+    o, os_ = run_oracle(w, 3)
+    compare_states(p.export(), o.export_local(), TOL64)
+    for g, r in zip(gs, os_):
+        assert g["updated_ps"] == r["updates"]
+        assert g["blocks"] == r["blocks"]
+        assert abs(g["pruned_mass"] - r["pruned_mass"]) <= 1e-12 * r["mass_before"]
+
+
+def test_26_neighbour_buffer_at_the_mesh_edges():
+    """Random content on a 3 x 2 x 3-block mesh, so content blocks sit on the
+    faces, edges and corners of the velocity mesh and the buffer is clipped
+    there."""
+    n, nblk = (5, 4, 6), (3, 2, 3)
+    st = random_state(n, nblk, 35, density=0.3, zero_frac=0.2)
+    w = W.Workload("random26", n, (6.0, 5.0, 7.0), nblk, (-6.0, -4.0, -6.0), (1.0, 1.0, 1.0), 1.0, 3,
+                   6e-10, 26, B.VL_F64, (0, 1, 2), *st)
+    print_case("26-neighbour buffer, random content at the mesh edges")
+    p = gpu_partition(w)
+    gs = run_gpu(p, w.dt, 3, stats=True)
+    o, os_ = run_oracle(w, 3)
+    compare_states(p.export(), o.export_local(), TOL64)
+    assert any(r["pruned_mass"] > 0 for r in os_)
+    for g, r in zip(gs, os_):
+        assert g["blocks"] == r["blocks"]

@@ -369,3 +369,87 @@ def test_pruning_threshold_is_inclusive():
             assert np.array_equal(f[(o[c] + k) * 64:(o[c] + k + 1) * 64], dense[c, b])
     kept = sum(dense[c, list(want[c])].sum() for c in range(4))
     assert s["pruned_mass"] == pytest.approx((dense.sum() - kept) * 1000.0, rel=1e-12)
+
+
+def _prune_only(dense, nblk, T, vbuffer):
+    """dt = 0: the step reduces to the end-of-step pruning of the input."""
+    n = (dense.shape[0], 1, 1)
+    p = make(n, sparse_min=T, vbuffer=vbuffer, nblk=nblk, vmin=(-8.0, -6.0, -6.0),
+             dx=(10.0, 10.0, 10.0))
+    p.load_local(*dense_to_csr(dense))
+    p.fill_ghosts()
+    s = p.step(0.0)
+    o, i, f = p.export_local()
+    return s, [set(int(b) for b in i[o[c]:o[c + 1]]) for c in range(dense.shape[0])], (o, i, f)
+
+
+def test_pruning_with_the_26_neighbour_buffer_hand_worked():
+    """The velocity-space buffer of all 26 neighbours (Section 2's 'one
+    neighbour-block buffer' read as every block touching a content block),
+    clipped at the edges and corners of the mesh.  Mesh 4 x 3 x 3 blocks, id =
+    bx + 4 (by + 3 bz).  The expected sets below were enumerated by hand.
+      cell 0: content (1,1,1) = 17, inside the mesh: the 3x3x3 cube around it
+      cell 1: content (3,2,2) = 35, the far corner: a 2x2x2 cube
+      cell 2: content (0,0,1) = 12, on an edge of the mesh: 2x2x3 blocks
+      cell 3: content (0,0,0) = 0 and (2,2,2) = 34; block 17 = (1,1,1) is
+              held (below the threshold) and touches both only through a
+              corner: kept with 26 neighbours, removed with 6."""
+    nblk = (4, 3, 3)
+    NB = 36
+    T = 1e-3
+    rng = np.random.default_rng(23)
+    dense = rng.uniform(0.0, 0.5 * T, (4, NB, 64))
+    for c in range(4):   # only the listed content blocks reach the threshold
+        assert np.all(dense[c] < T)
+    dense[0, 17, 40] = T
+    dense[1, 35, 0] = 3 * T
+    dense[2, 12, 63] = 2 * T
+    dense[3, 0, 5] = 2 * T
+    dense[3, 34, 21] = T
+    want26 = [
+        {0, 1, 2, 4, 5, 6, 8, 9, 10, 12, 13, 14, 16, 17, 18, 20, 21, 22,
+         24, 25, 26, 28, 29, 30, 32, 33, 34},
+        {18, 19, 22, 23, 30, 31, 34, 35},
+        {0, 1, 4, 5, 12, 13, 16, 17, 24, 25, 28, 29},
+        {0, 1, 4, 5, 12, 13, 16, 17, 18, 19, 21, 22, 23, 29, 30, 31, 33, 34, 35},
+    ]
+    want6 = [
+        {17, 16, 18, 13, 21, 5, 29},
+        {35, 34, 31, 23},
+        {12, 13, 16, 0, 24},
+        {0, 1, 4, 12, 34, 33, 35, 30, 22},
+    ]
+    assert len(want26[0]) == 27 and len(want26[1]) == 8 and len(want26[2]) == 12
+    for vb, want in ((26, want26), (6, want6)):
+        s, got, (o, i, f) = _prune_only(dense, nblk, T, vb)
+        assert got == want, vb
+        for c in range(4):
+            for k, b in enumerate(i[o[c]:o[c + 1]]):
+                assert np.array_equal(f[(o[c] + k) * 64:(o[c] + k + 1) * 64], dense[c, b])
+        kept = sum(dense[c, sorted(want[c])].sum() for c in range(4))
+        assert s["pruned_mass"] == pytest.approx((dense.sum() - kept) * 1000.0, rel=1e-12)
+    # the corner-only neighbour is what tells the two buffers apart
+    assert 17 in want26[3] and 17 not in want6[3]
+    # without a buffer only the content blocks stay
+    _, got0, _ = _prune_only(dense, nblk, T, 0)
+    assert got0 == [{17}, {35}, {12}, {0, 34}]
+
+
+def test_pruning_creates_zero_blocks_in_the_26_neighbour_buffer():
+    """A content block whose diagonal neighbours are absent gets them as new,
+    zero blocks (the list is the dilated set, not the old list)."""
+    nblk = (3, 3, 3)
+    NB = 27
+    T = 1.0
+    n = (1, 1, 1)
+    p = make(n, sparse_min=T, vbuffer=26, nblk=nblk, vmin=(-6.0, -6.0, -6.0), dx=(10.0, 10.0, 10.0))
+    f = np.full(64, 0.25)
+    f[7] = 2.0
+    p.load_local(np.array([0, 1], np.int64), np.array([13], np.int32), f)   # the centre block only
+    p.fill_ghosts()
+    p.step(0.0)
+    o, i, g = p.export_local()
+    assert list(i) == list(range(27))
+    g = g.reshape(27, 64)
+    assert np.array_equal(g[13], f)
+    assert not np.any(np.delete(g, 13, axis=0))
