@@ -22,9 +22,9 @@ constexpr int RED_DOUBLES = 1024;
 inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-    size_t pool, ring, lstart, lcount, lcapa, lsorted, lid, lslot, litem, rows, items, masks, ctl, cover, cellred,
-        red, cellcnt, total;
-    int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap;
+    size_t pool, ring, lstart, lcount, lcapa, lsorted, lid, lslot, litem, rows, items, masks, resid, penfirst,
+        pencnt, pensum, ctl, cover, cellred, red, cellcnt, total;
+    int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap, pen_cap;
     int wlmax, cover_stride;
 };
 
@@ -71,6 +71,7 @@ Layout make_layout(const vl_desc *d)
     L.row_cap = lcap + gcap + 64;
     const int64_t tot = lcap + gcap;
     L.item_cap = tot <= (1 << 24) ? tot + 64 : std::max<int64_t>(1 << 24, tot / 4);
+    L.pen_cap = std::max(P[0] * P[1], std::max(P[0] * P[2], P[1] * P[2]));
     int maxP = std::max(P[0], std::max(P[1], P[2]));
     L.wlmax = (maxP + 31) / 32;
     int maxnv = 4 * std::max(d->nblk[0], std::max(d->nblk[1], d->nblk[2]));
@@ -90,6 +91,10 @@ Layout make_layout(const vl_desc *d)
     L.rows = o;    o = align_up(o + (size_t)L.row_cap * 4);
     L.items = o;   o = align_up(o + (size_t)L.item_cap * sizeof(Item));
     L.masks = o;   o = align_up(o + (size_t)L.item_cap * L.wlmax * 4);
+    L.resid = o;   o = align_up(o + (d->storage == VL_F64 ? 0 : (size_t)L.item_cap * 8));
+    L.penfirst = o; o = align_up(o + (size_t)L.pen_cap * 8);
+    L.pencnt = o;  o = align_up(o + (size_t)L.pen_cap * 4);
+    L.pensum = o;  o = align_up(o + (size_t)L.pen_cap * 8);
     L.ctl = o;     o = align_up(o + sizeof(Ctl));
     L.cover = o;   o = align_up(o + (size_t)3 * maxnv * 8);
     L.cellred = o; o = align_up(o + (size_t)L.nlocal * 8);
@@ -221,7 +226,9 @@ void update_box(const vl_partition *p, int mode, int s, int lo[3], int hi[3])
 // The kernels of one translation step (growth, work list and shear per axis,
 // then pruning into the other local list region), enqueued on st with no
 // host read-back, so that the sequence can also be captured into a graph.
-void enqueue_translate(vl_partition *p, double dt, int mode, double *ledger, hipStream_t st)
+// ledger3 (device, optional): the FP64 rounding residuals that each shear
+// leaves outside f on the local pencils, one sum per shear.
+void enqueue_translate(vl_partition *p, double dt, int mode, double *ledger3, hipStream_t st)
 {
     const Dev &D = p->D;
     const int nxt = 1 - p->cur;
@@ -253,8 +260,9 @@ void enqueue_translate(vl_partition *p, double dt, int mode, double *ledger, hip
         }
         {
             ProfScope ps(p, K_SHEAR0 + s);
-            launch_sweep(D, d, s, lo, hi, dt, s == 2, ledger, st);
+            launch_sweep(D, d, s, lo, hi, dt, s == 2, st);
         }
+        if (ledger3) launch_ledger_sum(D, d, lo, hi, ledger3 + s, st);
     }
     launch_book(D, nxt == 0 ? BOOK_PRUNE_RESET_A : BOOK_PRUNE_RESET_B, st);
     {
@@ -297,7 +305,7 @@ int capture_step(vl_partition *p, double dt, int mode)
     p->prof.on = false;  // no event records inside the graph
     VL_HIP(hipStreamBeginCapture(g.cap, hipStreamCaptureModeRelaxed));
     if (mode == VL_COALESCED) enqueue_fill(p, g.cap);
-    enqueue_translate(p, dt, mode, p->D.red + 4, g.cap);
+    enqueue_translate(p, dt, mode, nullptr, g.cap);
     hipGraph_t graph = nullptr;
     const hipError_t le = hipGetLastError();
     const hipError_t ee = hipStreamEndCapture(g.cap, &graph);
@@ -422,6 +430,11 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
     D.items = (Item *)(w + L.items);
     D.masks = (uint32_t *)(w + L.masks);
     D.item_cap = L.item_cap;
+    D.resid = (double *)(w + L.resid);
+    D.pen_first = (int64_t *)(w + L.penfirst);
+    D.pen_cnt = (int32_t *)(w + L.pencnt);
+    D.pen_sum = (double *)(w + L.pensum);
+    D.pen_cap = L.pen_cap;
     D.wlmax = L.wlmax;
     D.ctl = (Ctl *)(w + L.ctl);
     D.cover = nullptr;
@@ -600,9 +613,8 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
     if (stats) {
         launch_cell_mass(D, st);
         launch_reduce(D, D.cell_red, D.nlocal, D.red + 0, st);
-        VL_HIP(hipMemsetAsync(D.red + 3, 0, sizeof(double), st));  // ledger of this step
     }
-    enqueue_translate(p, dt, mode, stats ? D.red + 3 : D.red + 4, st);
+    enqueue_translate(p, dt, mode, stats ? D.red + 8 : nullptr, st);
     const int nxt = 1 - p->cur;
     VL_HIP(hipGetLastError());
     p->cur = nxt;
@@ -613,7 +625,7 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
         launch_reduce(D, D.cell_red, D.nlocal, D.red + 1, st);
         launch_cell_counts(D, st);
         VL_HIP(hipGetLastError());
-        double red[4];
+        double red[11];
         Ctl ctl;
         std::vector<int32_t> cc((size_t)D.nlocal);
         VL_HIP(hipMemcpyAsync(red, D.red, sizeof(red), hipMemcpyDeviceToHost, st));
@@ -625,7 +637,7 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
         stats->mass_before = red[0] * vol;
         stats->mass_after = red[1] * vol;
         stats->pruned_mass = red[2];
-        stats->ledger_mass = red[3] * vol;
+        stats->ledger_mass = ((red[8] + red[9]) + red[10]) * vol;
         int64_t nb = 0;
         for (int32_t v : cc) nb += v;
         stats->local_blocks = nb;

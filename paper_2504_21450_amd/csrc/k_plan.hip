@@ -7,11 +7,13 @@
 //   3. grows the block lists of the updated cells: a cell gains every block of
 //      its upwind face neighbour that moves into it (bit shifts of the
 //      presence masks), allocating slots for the new blocks,
-//   4. emits one work item per block held by an updated cell: its id, its
-//      presence mask and a compacted row of the slots of the cells holding it;
-//      in the last shear of a step it also records, per list entry of the
-//      pencil's cells, the item of the entry's block (where the shear leaves
-//      the content flags that the pruning reads).
+//   4. emits one work item per block of the union, in ascending id order and
+//      contiguous per pencil (taken with one counter update per pencil): for
+//      a block held by an updated cell its presence mask and a compacted row
+//      of the slots of the cells holding it, for any other block an empty
+//      item; in the last shear of a step it also records, per list entry of
+//      the pencil's cells, the item of the entry's block (where the shear
+//      leaves the content flags that the pruning reads).
 // Each cell belongs to exactly one pencil of a shear, so the workgroup owns the
 // lists it grows.  Block ids of a chunk of the union are processed at a time
 // so the LDS footprint is bounded.
@@ -82,7 +84,8 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_tmp[256];
     __shared__ long long s_ll[256];
-    __shared__ unsigned long long s_base[4];  // item, row, new-slot bases, status
+    __shared__ unsigned long long s_base[4];  // (unused), row, new-slot bases, status
+    __shared__ long long s_ibp;               // the pencil's first item
     const int tid = threadIdx.x;
     const int L = pp.L, WL = pp.WL, W = D.W, R = pp.R;
 
@@ -171,6 +174,18 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     for (int w = tid; w < W; w += 256) s_rank[w] = popc(s_bm[w]);
     __syncthreads();
     const int U = block_scan_excl(s_rank, W, s_tmp);
+    // the pencil's items: item first + r for the block of union rank r
+    if (tid == 0) {
+        const unsigned long long ib = U > 0 ? atomicAdd(&D.ctl->n_items, (unsigned long long)U) : 0ull;
+        if ((int64_t)(ib + U) > D.item_cap) atomicOr(&D.ctl->err, (unsigned long long)E_ITEMS);
+        s_ibp = (long long)ib;
+        if (p < D.pen_cap) {
+            D.pen_first[p] = (int64_t)ib;
+            D.pen_cnt[p] = U;
+        }
+    }
+    __syncthreads();
+    const int64_t ibp = (int64_t)s_ibp;
 
     // update-range mask
     uint32_t um[MAXWL];
@@ -323,9 +338,8 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         // cells (coalesced; the old places are not reused within the step)
         for (int i = tid; i < L; i += 256) {
             s_mvn[i] = 0;
-            const int req = s_req[i];
+            const int req = s_req[i];  // cleared when the cell's new entries are written
             if (req == 0) continue;
-            s_req[i] = 0;
             const int have = s_cnt[i] + s_new[i];
             if (have + req <= s_cap[i]) continue;
             const int ncap = (have + req) + (have + req) / 2 + 32;
@@ -365,7 +379,6 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
             s_ro[rn] = nrow;
             s_np[rn] = nnew;
             unsigned long long err = 0;
-            unsigned long long ib = atomicAdd(&D.ctl->n_items, (unsigned long long)nact);
             unsigned long long rb = atomicAdd(&D.ctl->row_top, (unsigned long long)nrow);
             unsigned long long nb = 0;
             unsigned long long ok = 1;
@@ -373,7 +386,6 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                 err |= E_ROWS;
                 ok = 0;
             }
-            if ((int64_t)(ib + nact) > D.item_cap) err |= E_ITEMS;
             if (nnew > 0) {
                 if (local_pencil) {
                     nb = atomicAdd(&D.ctl->ring_head, (unsigned long long)nnew);
@@ -390,20 +402,29 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                 }
             }
             if (err) atomicOr(&D.ctl->err, err);
-            s_base[0] = ib;
             s_base[1] = rb;
             s_base[2] = nb;
             s_base[3] = ok;
         }
         __syncthreads();
-        const unsigned long long ib = s_base[0], rb = s_base[1], nb = s_base[2];
+        const unsigned long long rb = s_base[1], nb = s_base[2];
         const bool rows_ok = (s_base[3] & 1) != 0;
         const bool alloc_failed = (s_base[3] & 2) != 0;
 
         // items and new blocks
         for (int k = tid; k < rn; k += 256) {
-            if (s_ai[k + 1] == s_ai[k]) continue;  // inactive
-            const int64_t it = (int64_t)ib + s_ai[k];
+            const int64_t it = ibp + r0 + k;
+            if (s_ai[k + 1] == s_ai[k]) {  // no updated cell holds the block: empty item
+                if (it < D.item_cap) {
+                    Item item;
+                    item.id = s_id[k];
+                    item.pencil = p;
+                    item.rowoff = 0;
+                    D.items[it] = item;
+                    for (int w = 0; w < D.wlmax; w++) D.masks[it * D.wlmax + w] = 0u;
+                }
+                continue;
+            }
             const int64_t rowoff = (int64_t)rb + s_ro[k];
             if (it < D.item_cap) {
                 Item item;
@@ -436,17 +457,37 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                         pos += popc(s_pres[k * WL + w] & ((1u << bit) - 1u));
                         D.rows[rowoff + pos] = (int32_t)((uint32_t)slot | NEWFLAG);
                     }
-                    if (!alloc_failed) {
-                        const int lp = atomicAdd(&s_new[i], 1);
-                        if (s_cnt[i] + lp < s_cap[i]) {
-                            const int64_t at = s_cs[i] + s_cnt[i] + lp;
-                            D.lid[at] = s_id[k];
-                            D.lslot[at] = (int32_t)slot;
-                            if (last) __builtin_nontemporal_store((int32_t)it, &D.litem[at]);
-                        } else {
-                            atomicOr(&D.ctl->err, (unsigned long long)E_LIST);
-                        }
-                    }
+                }
+            }
+        }
+        // the new list entries, per cell in ascending block id (the same order
+        // in every run): the slot of the block of chunk rank k new in cell i is
+        // the one the row above took, number s_np[k] + (rank of i among k's
+        // new cells) of this chunk's allocation
+        for (int i = tid; i < L; i += 256) {
+            int want = s_req[i];
+            if (want == 0) continue;
+            s_req[i] = 0;
+            if (alloc_failed) continue;
+            const int iw = i >> 5;
+            const uint32_t ibit = 1u << (i & 31);
+            for (int k = 0; k < rn && want > 0; k++) {
+                const uint32_t nw = s_newb[k * WL + iw];
+                if (!(nw & ibit)) continue;
+                want--;
+                int qn = s_np[k];
+                for (int w2 = 0; w2 < iw; w2++) qn += popc(s_newb[k * WL + w2]);
+                qn += popc(nw & (ibit - 1u));
+                const int64_t slot = local_pencil ? (int64_t)D.ring[(int64_t)((nb + qn) % (unsigned long long)D.lcap)]
+                                                  : D.lcap + (int64_t)nb + qn;
+                const int lp = s_new[i]++;
+                if (s_cnt[i] + lp < s_cap[i]) {
+                    const int64_t at = s_cs[i] + s_cnt[i] + lp;
+                    D.lid[at] = s_id[k];
+                    D.lslot[at] = (int32_t)slot;
+                    if (last) __builtin_nontemporal_store((int32_t)(ibp + r0 + k), &D.litem[at]);
+                } else {
+                    atomicOr(&D.ctl->err, (unsigned long long)E_LIST);
                 }
             }
         }
@@ -504,7 +545,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                         for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
                         pos += popc(s_pres[k * WL + iw] & below);
                         D.rows[(int64_t)rb + s_ro[k] + pos] = sls[kk];
-                        if (last) __builtin_nontemporal_store((int32_t)((int64_t)ib + s_ai[k]), &D.litem[at0 + e0 + 64 * kk]);
+                        if (last) __builtin_nontemporal_store((int32_t)(ibp + r0 + k), &D.litem[at0 + e0 + 64 * kk]);
                     }
                 }
                 // the tail
@@ -519,7 +560,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                     for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
                     pos += popc(s_pres[k * WL + iw] & below);
                     D.rows[(int64_t)rb + s_ro[k] + pos] = pre ? tsl0 : D.lslot[cs + e];
-                    if (last) __builtin_nontemporal_store((int32_t)((int64_t)ib + s_ai[k]), &D.litem[cs + e]);
+                    if (last) __builtin_nontemporal_store((int32_t)(ibp + r0 + k), &D.litem[cs + e]);
                 }
             }
         }

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
     __shared__ unsigned long long s_base[3];
     __shared__ unsigned long long s_rbase;
     __shared__ int s_cnt[4];
+    __shared__ int s_wrem[4];
     __shared__ int s_fail;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int W = D.W;
@@ -162,23 +163,42 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
             s_eid[e] = D.lid[cs + e0 + e];
             s_eslot[e] = D.lslot[cs + e0 + e];
         }
-        if (tid == 0) s_cnt[2] = 0;
         __syncthreads();
-        for (int e = tid; e < m; e += 256) {
-            const int32_t id = s_eid[e];
-            const int32_t slot = s_eslot[e];
-            const int w = id >> 5;
-            const uint32_t bit = 1u << (id & 31);
-            if (s_keep[w] & bit) {
-                const int pos = s_rank[w] + popc32(s_keep[w] & (bit - 1u));
-                D.lid[ns + pos] = id;
-                D.lslot[ns + pos] = slot;
-            } else {
-                const int k = atomicAdd(&s_cnt[2], 1);
+        // removed entries are queued in entry order (a prefix count over the
+        // workgroup per 256 entries), so their mass is summed in the same order
+        // in every run
+        int nrem_run = 0;
+        for (int r = 0; r < m; r += 256) {
+            const int e = r + tid;
+            bool removed = false;
+            int32_t slot = 0;
+            if (e < m) {
+                const int32_t id = s_eid[e];
+                slot = s_eslot[e];
+                const int w = id >> 5;
+                const uint32_t bit = 1u << (id & 31);
+                if (s_keep[w] & bit) {
+                    const int pos = s_rank[w] + popc32(s_keep[w] & (bit - 1u));
+                    D.lid[ns + pos] = id;
+                    D.lslot[ns + pos] = slot;
+                } else {
+                    removed = true;
+                }
+            }
+            const unsigned long long bal = __ballot(removed);
+            if (lane == 0) s_wrem[wv] = (int)__popcll(bal);
+            __syncthreads();
+            int before = nrem_run;
+            for (int j = 0; j < wv; j++) before += s_wrem[j];
+            const int k = before + (int)__popcll(bal & ((1ull << lane) - 1ull));
+            if (removed) {
                 if (k < PR_QUEUE) s_q[k] = slot;
                 else s_eslot[e] = -1 - slot;  // summed below from the staged entries
             }
+            nrem_run += ((s_wrem[0] + s_wrem[1]) + s_wrem[2]) + s_wrem[3];
+            __syncthreads();
         }
+        if (tid == 0) s_cnt[2] = nrem_run;
         __syncthreads();
         // return the removed slots to the free ring: one counter update per chunk
         {

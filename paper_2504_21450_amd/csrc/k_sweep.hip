@@ -16,10 +16,12 @@
 //   VL_F64 : everything in FP64.
 //   VL_F32 / VL_BF16 : values are loaded into FP32; slopes, faces and the
 //            limiter run in FP32; the Courant number, flux integral and update
-//            in FP64.  The FP64 update is rounded to the storage type and the
-//            rounding residual is carried along the pencil into the next
-//            updated cell, so a pencil's mass changes only by its final
-//            residual, which is accumulated in an FP64 ledger.
+//            in FP64.  The FP64 update plus the carry is rounded to the
+//            storage type (a negative sum is stored as zero) and the
+//            difference is carried along the pencil into the next updated
+//            cell, so a pencil's mass changes only by its final residual,
+//            which the item leaves (summed over its 64 lanes in a fixed order)
+//            for the FP64 mass ledger.
 #include "vl_internal.h"
 #include "vl_storage.h"
 
@@ -30,7 +32,6 @@ struct SweepParams {
     int e1, e2, lo1, n1, lo2;  // pencil geometry (to tell local pencils)
     double dt;
     double sparse_min;
-    double *ledger;            // FP64 accumulator of terminal residuals (mixed storage)
 };
 
 __device__ inline void wave_sync_lds()
@@ -44,6 +45,13 @@ constexpr uint32_t ABSENT = 0xffffffffu;
 constexpr int PF = 8;  // cells prefetched ahead of the reconstruction front
 
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// sum over the wavefront's 64 lanes, the same pairing every time
+__device__ __forceinline__ double wave_sum64(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
 
 // max(0, min(x, y)); in FP32 one median-of-three instruction (x >= 0 here,
 // and a zero result takes the sign of the side afterwards, so the sign of a
@@ -197,12 +205,13 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
                 *(double *)(dst + lane_off) = nv;
             } else {
                 const double x = (double)a3 + (Ff_prev - Ff) + (live ? carry : 0.0);
+                const double xs = fmax(x, 0.0);  // no negative density is stored
                 if constexpr (ST == VL_F32) {
-                    const float q = (float)x;
+                    const float q = (float)xs;
                     nv = (double)q;
                     *(float *)(dst + lane_off) = q;
                 } else {
-                    const uint16_t h = bf16_rne_f64(x);
+                    const uint16_t h = bf16_rne_f64(xs);
                     nv = (double)bf16_to_f32(h);
                     *(uint16_t *)(dst + lane_off) = h;
                 }
@@ -287,12 +296,13 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
                         block_store(dst, lane_off, nv);
                     } else {
                         const double x = (double)a3 + (Ff_prev - Ff) + carry;
+                        const double xs = fmax(x, 0.0);  // no negative density is stored
                         if constexpr (ST == VL_F32) {
-                            const float q = (float)x;
+                            const float q = (float)xs;
                             nv = (double)q;
                             block_store(dst, lane_off, q);
                         } else {
-                            const uint16_t h = bf16_rne_f64(x);
+                            const uint16_t h = bf16_rne_f64(xs);
                             nv = (double)bf16_to_f32(h);
                             block_store(dst, lane_off, h);
                         }
@@ -397,7 +407,6 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     uint32_t *srow = s_slot[wv];
     uint32_t *sseg = s_seg[wv];
-    double ledger_acc = 0.0;
 
     for (int64_t it = (int64_t)blockIdx.x * 4 + wv; it < nitems; it += nwaves) {
         const Item item = D.items[it];
@@ -413,7 +422,11 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
                 m[w] = (w < WL) ? __builtin_amdgcn_readfirstlane(D.masks[it * D.wlmax + w]) : 0u;
                 pre[w + 1] = pre[w] + __popc(m[w]);
             }
-            if (pre[MAXWL] == 0) continue;
+            if (pre[MAXWL] == 0) {  // empty item: no line, no residual
+                if constexpr (ST != VL_F64)
+                    if (lane == 0) D.resid[it] = 0.0;
+                continue;
+            }
 #pragma unroll
             for (int w = 0; w < MAXWL; w++) {
                 const uint32_t a0 = ~m[w], a1 = (w + 1 < MAXWL) ? ~m[w + 1] : ~0u;
@@ -477,19 +490,12 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
         }
 
         if constexpr (ST != VL_F64) {
-            // terminal residual of this pencil line; ghost pencils duplicate
-            // local ones and are not counted
-            const int p = item.pencil;
-            const int t1 = sp.lo1 + p % sp.n1, t2 = sp.lo2 + p / sp.n1;
-            const bool local = t1 >= H && t1 < H + D.n[sp.e1] && t2 >= H && t2 < H + D.n[sp.e2];
-            if (local) ledger_acc += carry;
+            // terminal residual of the item's pencil line (the ledger takes
+            // those of the local pencils)
+            const double r = wave_sum64(carry);
+            if (lane == 0) D.resid[it] = r;
         }
         wave_sync_lds();
-    }
-    if constexpr (ST != VL_F64) {
-        double s = ledger_acc;
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        if (lane == 0 && s != 0.0) atomicAdd(sp.ledger, s);
     }
 }
 
@@ -595,12 +601,13 @@ __device__ __forceinline__ void march_stream(const Dev &D, const uint32_t *X, co
                         *(double *)(dst + lane_off) = nv;
                     } else {
                         const double x = (double)a3 + (Ff_prev - Ff) + carry;
+                        const double xs = fmax(x, 0.0);  // no negative density is stored
                         if constexpr (ST == VL_F32) {
-                            const float q = (float)x;
+                            const float q = (float)xs;
                             nv = (double)q;
                             *(float *)(dst + lane_off) = q;
                         } else {
-                            const uint16_t h = bf16_rne_f64(x);
+                            const uint16_t h = bf16_rne_f64(xs);
                             nv = (double)bf16_to_f32(h);
                             *(uint16_t *)(dst + lane_off) = h;
                         }
@@ -636,7 +643,6 @@ __device__ __forceinline__ void sweep_stream(const Dev &D, const SweepParams &sp
     const int ld = (d == 0) ? (lane & 3) : (d == 1) ? ((lane >> 2) & 3) : (lane >> 4);
     const int64_t nitems = min((int64_t)D.ctl->n_items, D.item_cap);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
-    double ledger_acc = 0.0;
     int64_t it = (int64_t)blockIdx.x * 4 + wv;
     if (it >= nitems) return;
     uint32_t *X = s_tab[wv][0], *Y = s_tab[wv][1];
@@ -680,20 +686,13 @@ __device__ __forceinline__ void sweep_stream(const Dev &D, const SweepParams &sp
             store_flag_words(D, it, X, sflag, L, lane);
         }
         if constexpr (ST != VL_F64) {
-            const int p = D.items[it].pencil;
-            const int t1 = sp.lo1 + p % sp.n1, t2 = sp.lo2 + p / sp.n1;
-            const bool local = t1 >= H && t1 < H + D.n[sp.e1] && t2 >= H && t2 < H + D.n[sp.e2];
-            if (local) ledger_acc += carry;
+            const double r = wave_sum64(carry);  // terminal residual of the line
+            if (lane == 0) D.resid[it] = r;
         }
         wave_sync_lds();
         uint32_t *tmp = X;
         X = Y;
         Y = tmp;
-    }
-    if constexpr (ST != VL_F64) {
-        double sum = ledger_acc;
-        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-        if (lane == 0 && sum != 0.0) atomicAdd(sp.ledger, sum);
     }
 }
 
@@ -768,7 +767,7 @@ static void launch_st(const Dev &D, const SweepParams &sp, int v, hipStream_t st
 int sweep_variants() { return NVARIANTS; }
 
 void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, bool last,
-                  double *ledger, hipStream_t st)
+                  hipStream_t st)
 {
     SweepParams sp;
     sp.d = d;
@@ -782,13 +781,65 @@ void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3
     sp.lo2 = lo[sp.e2];
     sp.dt = dt;
     sp.sparse_min = D.sparse_min;
-    sp.ledger = ledger;
     const int v = (D.sweep_variant[sidx] >= 0 && D.sweep_variant[sidx] < NVARIANTS) ? D.sweep_variant[sidx] : 0;
     switch (D.storage) {
     case VL_F64: last ? launch_st<VL_F64, true>(D, sp, v, st) : launch_st<VL_F64, false>(D, sp, v, st); break;
     case VL_F32: last ? launch_st<VL_F32, true>(D, sp, v, st) : launch_st<VL_F32, false>(D, sp, v, st); break;
     default: last ? launch_st<VL_BF16, true>(D, sp, v, st) : launch_st<VL_BF16, false>(D, sp, v, st); break;
     }
+}
+
+// ---------------------------------------------------------------------------
+// mass ledger of one shear: the terminal residuals of the local pencils'
+// items, summed per pencil over its items (ascending block id) by one
+// wavefront, then over the pencils in order by one workgroup; no atomics, so
+// the total is the same in every run
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ledger_pencils(Dev D, int e1, int e2, int lo1, int n1, int lo2,
+                                                        int64_t npen, double *pen_sum)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= npen || failed(D)) return;
+    const int t1 = lo1 + (int)(p % n1), t2 = lo2 + (int)(p / n1);
+    const bool local = t1 >= H && t1 < H + D.n[e1] && t2 >= H && t2 < H + D.n[e2];
+    double acc = 0.0;
+    if (local && p < D.pen_cap) {
+        const int64_t first = D.pen_first[p];
+        const int64_t cnt = min((int64_t)D.pen_cnt[p], max((int64_t)0, D.item_cap - first));
+        for (int64_t k = lane; k < cnt; k += 64) acc += D.resid[first + k];
+    }
+    acc = wave_sum64(acc);
+    if (lane == 0) pen_sum[p] = acc;
+}
+
+__global__ __launch_bounds__(1024) void k_sum_fixed(const double *in, int64_t n, double *out)
+{
+    __shared__ double s[1024];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) acc += in[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+void launch_ledger_sum(const Dev &D, int d, const int lo[3], const int hi[3], double *out, hipStream_t st)
+{
+    const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
+    const int n1 = hi[e1] - lo[e1], n2 = hi[e2] - lo[e2];
+    const int64_t npen = (int64_t)n1 * n2;
+    if (npen <= 0 || D.storage == VL_F64) {
+        hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, st, D.cell_red, (int64_t)0, out);
+        return;
+    }
+    // per-pencil sums in the scratch of per-cell sums (npen <= padded cells)
+    hipLaunchKernelGGL(k_ledger_pencils, dim3((unsigned)((npen + 3) / 4)), dim3(256), 0, st, D, e1, e2, lo[e1],
+                       n1, lo[e2], npen, D.pen_sum);
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, st, D.pen_sum, npen, out);
 }
 
 }  // namespace vl

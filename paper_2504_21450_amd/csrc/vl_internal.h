@@ -19,7 +19,14 @@
 //             sorted again by the pruning.
 //   rows    : per shear, for each (pencil, block) work item the slots of the
 //             cells of the pencil that hold the block (compacted, pencil order).
-//   items   : per shear, block id, row offset and presence mask of every item.
+//   items   : per shear, block id, row offset and presence mask of every item;
+//             the items of one pencil are contiguous, one per block of the
+//             union of the pencil's lists in ascending id order (blocks with no
+//             updated cell get an empty item), so pencil p's items are
+//             [pen_first[p], pen_first[p] + pen_cnt[p]).
+//   resid   : per item, the FP32/BF16 rounding residual left at the end of the
+//             item's pencil line, summed over the block's 64 velocity cells
+//             (FP64), reduced per pencil in a fixed order for the mass ledger.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -87,6 +94,11 @@ struct Dev {
     uint32_t *masks;         // per item: presence along the pencil; after the last
                              // shear, the content flags of the updated cells
     int64_t item_cap;
+    double *resid;           // per item: terminal rounding residual of its line (item_cap)
+    int64_t *pen_first;      // per pencil of the current shear: first item
+    int32_t *pen_cnt;        //   and number of items (pen_cap entries)
+    double *pen_sum;         //   and the sum of its items' residuals (ledger scratch)
+    int64_t pen_cap;
     int wlmax;
     Ctl *ctl;
     const double *cover;     // Courant override (3 x cover_stride) or null
@@ -171,7 +183,10 @@ void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3]
                  hipStream_t st);
 int sweep_variants();
 void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, bool last,
-                  double *ledger, hipStream_t st);
+                  hipStream_t st);
+// FP64 sum of the terminal residuals of the shear's local pencils into *out:
+// per pencil over its items in id order, then over the pencils in order
+void launch_ledger_sum(const Dev &D, int d, const int lo[3], const int hi[3], double *out, hipStream_t st);
 void launch_prune(const Dev &D, int nxt_region, int last_axis, hipStream_t st);
 void launch_cell_mass(const Dev &D, hipStream_t st);
 void launch_reduce(const Dev &D, const double *in, int64_t n, double *out, hipStream_t st);

@@ -54,7 +54,7 @@ def test_reduced_storage_error_and_mass_table(reference, storage, name):
     w, snaps = reference
     NB = int(np.prod(w.nblk))
     print_case("%s storage, 100 steps against the oracle" % name)
-    p = gpu_partition(w, storage=storage, slack=3.0)
+    p = gpu_partition(w, storage=storage, slack=6.0)
     m0 = None
     pruned = 0.0
     ledger = 0.0

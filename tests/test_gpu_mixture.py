@@ -101,10 +101,19 @@ def test_mixture_reduced_storage_against_oracle(small, storage, tol):
     w = small
     print_case("mixture storage %d step vs oracle sub-box" % storage)
     p = devsample.sample_partition(w, storage=storage)
+    for _ in range(3):
+        p.fill_ghosts()
+        s = p.step(w.dt, B.VL_COALESCED, stats=True)
+        resid = s["mass_before"] - (s["mass_after"] + s["pruned_mass"] + s["ledger_mass"])
+        assert abs(resid) <= 1e-12 * s["mass_before"]
+    # no negative density is stored, next to hot cells either (the carried
+    # rounding residual of a hot cell can exceed a cold neighbour's value)
+    _, _, f = p.export()
+    assert f.size and np.min(f) >= 0.0
+    p.close()
+    p = devsample.sample_partition(w, storage=storage)
     p.fill_ghosts()
-    s = p.step(w.dt, B.VL_COALESCED, stats=True)
-    resid = s["mass_before"] - (s["mass_after"] + s["pruned_mass"] + s["ledger_mass"])
-    assert abs(resid) <= 1e-12 * s["mass_before"]
+    p.step(w.dt, B.VL_COALESCED)
     lo = (9, 5, 3)
     err = compare(p.export_cells(subbox_local(w.n, lo)), oracle_subbox(w, lo), int(np.prod(w.nblk)), tol,
                   False)
