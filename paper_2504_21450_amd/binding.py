@@ -170,7 +170,7 @@ class Partition:
         # small partitions get room for a dense velocity mesh (no overflow
         # possible); large ones a multiple of the current block count
         if block_capacity is None:
-            block_capacity = int(nb * slack) + 64 * self.ncell + 1024
+            block_capacity = int(nb * slack) + 8 * self.ncell + 1024
             if self.ncell * NB <= 4_000_000:
                 block_capacity = max(block_capacity, self.ncell * NB + 1024)
         if ghost_block_capacity is None:

@@ -70,7 +70,9 @@ Layout make_layout(const vl_desc *d)
     L.LG = gcap + gcap / 2 + 32 * L.nghost;
     L.row_cap = lcap + gcap + 64;
     const int64_t tot = lcap + gcap;
-    L.item_cap = tot <= (1 << 24) ? tot + 64 : std::max<int64_t>(1 << 24, tot / 4);
+    // one item per block of a pencil's union: at most one per (cell, block)
+    // of the shear's box; large partitions hold many cells per item
+    L.item_cap = tot <= (1 << 24) ? tot + 64 : std::max<int64_t>(1 << 24, tot / 8);
     L.pen_cap = std::max(P[0] * P[1], std::max(P[0] * P[2], P[1] * P[2]));
     int maxP = std::max(P[0], std::max(P[1], P[2]));
     L.wlmax = (maxP + 31) / 32;

@@ -65,6 +65,27 @@ __device__ __forceinline__ C clamp_min0(C x, C y)
         return fmax((C)0, fmin(x, y));
 }
 
+// The FP64 update x of a cell (its carry included) in the storage type; a
+// negative sum is stored as zero.  nv receives the stored value in FP64, so
+// the caller carries x - nv on, which keeps the pencil's mass exact whatever
+// the rounding.  BF16: FP64 -> FP32 to nearest, then FP32 -> BF16 to nearest
+// even by the hardware conversion (two roundings; they differ from one
+// correct rounding only where the FP32 value lands on a BF16 midpoint).
+__device__ __forceinline__ float narrow_f32(double x, double &nv)
+{
+    const float q = fmaxf((float)x, 0.0f);
+    nv = (double)q;
+    return q;
+}
+__device__ __forceinline__ uint16_t narrow_bf16(double x, double &nv)
+{
+    float t = fmaxf((float)x, 0.0f);
+    __asm__("" : "+v"(t));  // keeps the two roundings apart (no fused FP64 -> BF16 rounding)
+    const uint16_t h = __builtin_bit_cast(uint16_t, (__bf16)t);
+    nv = (double)bf16_to_f32(h);
+    return h;
+}
+
 // One block (64 values of one cell) as a buffer resource: the block's address
 // is formed in scalar registers and each lane's value is at byte offset
 // lane * bytes, so no vector instruction computes addresses in the marches.
@@ -156,7 +177,8 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
             return bf16_to_f32(*(const uint16_t *)(blk + lane_off));
     };
 
-    C a1 = 0, a2 = 0, a3 = 0;   // a(t-1), a(t-2), a(t-3)
+    C a1 = 0, a2 = 0;           // a(t-1), a(t-2)
+    double a3d = 0.0;           // a(t-3) in FP64 (last iteration's a(t-2))
     C da_prev = 0;              // slope of cell t-2
     C face_prev = 0;            // face t-5/2
     double Fc_prev = 0.0, Ff_prev = 0.0;
@@ -189,7 +211,8 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
             const C mL = clamp_min0(fabs(dL), copysign((C)2.0, dL) * dR);
             const C mR = clamp_min0(fabs(dR), copysign((C)2.0, dR) * dL);
             const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
-            const double Fc = fma(P, dRp, fma(Q, dLp, c * (double)ai));
+            const double aid = (double)ai;
+            const double Fc = fma(P, dRp, fma(Q, dLp, c * aid));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
             // new value of cell t-3, stored unconditionally (to the sink when
             // there is nothing to store) so the memory counters stay exact
@@ -201,27 +224,21 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
             char *dst = (char *)D.pool + (uint64_t)s3 * (BLK * BS);
             double nv;
             if constexpr (ST == VL_F64) {
-                nv = (double)a3 + (Ff_prev - Ff);
+                nv = a3d + (Ff_prev - Ff);
                 *(double *)(dst + lane_off) = nv;
             } else {
-                const double x = (double)a3 + (Ff_prev - Ff) + (live ? carry : 0.0);
-                const double xs = fmax(x, 0.0);  // no negative density is stored
-                if constexpr (ST == VL_F32) {
-                    const float q = (float)xs;
-                    nv = (double)q;
-                    *(float *)(dst + lane_off) = q;
-                } else {
-                    const uint16_t h = bf16_rne_f64(xs);
-                    nv = (double)bf16_to_f32(h);
-                    *(uint16_t *)(dst + lane_off) = h;
-                }
+                const double x = a3d + (Ff_prev - Ff) + (live ? carry : 0.0);
+                if constexpr (ST == VL_F32)
+                    *(float *)(dst + lane_off) = narrow_f32(x, nv);
+                else
+                    *(uint16_t *)(dst + lane_off) = narrow_bf16(x, nv);
                 if (live) carry = x - nv;
             }
             if constexpr (LAST) {
                 const unsigned long long any = __ballot(nv >= smin);
                 if (t >= 3 && t < te) sflag[t - 3] = any ? 1 : 0;  // same value from every lane
             }
-            a3 = a2;
+            a3d = aid;
             a2 = a1;
             a1 = a;
             da_prev = da;
@@ -260,7 +277,8 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
         return block_load<ST>(block_rsrc<ST>(D, sl), lane_off);
     };
 
-    C a1 = 0, a2 = 0, a3 = 0;
+    C a1 = 0, a2 = 0;
+    double a3d = 0.0;
     C da_prev = 0;
     C face_prev = 0;
     double Fc_prev = 0.0, Ff_prev = 0.0;
@@ -284,7 +302,8 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
             const C mL = clamp_min0(fabs(dL), copysign((C)2.0, dL) * dR);
             const C mR = clamp_min0(fabs(dR), copysign((C)2.0, dR) * dL);
             const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
-            const double Fc = fma(P, dRp, fma(Q, dLp, c * (double)ai));
+            const double aid = (double)ai;
+            const double Fc = fma(P, dRp, fma(Q, dLp, c * aid));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
             if (t >= 6 && t < L && t < te) {  // past te: the next segment's march
                 const uint32_t sl3 = uniform_u32(srow[t - 3]);
@@ -292,20 +311,14 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
                     const __amdgpu_buffer_rsrc_t dst = block_rsrc<ST>(D, sl3 & ~NEWFLAG);
                     double nv;
                     if constexpr (ST == VL_F64) {
-                        nv = (double)a3 + (Ff_prev - Ff);
+                        nv = a3d + (Ff_prev - Ff);
                         block_store(dst, lane_off, nv);
                     } else {
-                        const double x = (double)a3 + (Ff_prev - Ff) + carry;
-                        const double xs = fmax(x, 0.0);  // no negative density is stored
-                        if constexpr (ST == VL_F32) {
-                            const float q = (float)xs;
-                            nv = (double)q;
-                            block_store(dst, lane_off, q);
-                        } else {
-                            const uint16_t h = bf16_rne_f64(xs);
-                            nv = (double)bf16_to_f32(h);
-                            block_store(dst, lane_off, h);
-                        }
+                        const double x = a3d + (Ff_prev - Ff) + carry;
+                        if constexpr (ST == VL_F32)
+                            block_store(dst, lane_off, narrow_f32(x, nv));
+                        else
+                            block_store(dst, lane_off, narrow_bf16(x, nv));
                         carry = x - nv;
                     }
                     if constexpr (LAST) {
@@ -314,7 +327,7 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
                     }
                 }
             }
-            a3 = a2;
+            a3d = aid;
             a2 = a1;
             a1 = a;
             da_prev = da;
@@ -564,8 +577,8 @@ __device__ __forceinline__ void march_stream(const Dev &D, const uint32_t *X, co
         else
             return bf16_to_f32(*(const uint16_t *)(blk + lane_off));
     };
-    C a1 = 0, a2 = 0, a3 = 0, da_prev = 0, face_prev = 0;
-    double Fc_prev = 0.0, Ff_prev = 0.0;
+    C a1 = 0, a2 = 0, da_prev = 0, face_prev = 0;
+    double a3d = 0.0, Fc_prev = 0.0, Ff_prev = 0.0;
     const int G = (L + 7) / 8;
     if (G == 1) build_next();
     for (int g = 0; g < G; g++) {
@@ -588,7 +601,8 @@ __device__ __forceinline__ void march_stream(const Dev &D, const uint32_t *X, co
             const C mL = clamp_min0(fabs(dL), copysign((C)2.0, dL) * dR);
             const C mR = clamp_min0(fabs(dR), copysign((C)2.0, dR) * dL);
             const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
-            const double Fc = fma(P, dRp, fma(Q, dLp, c * (double)ai));
+            const double aid = (double)ai;
+            const double Fc = fma(P, dRp, fma(Q, dLp, c * aid));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
             if (t >= 6 && t < L) {
                 const uint32_t sl3 = uniform_u32(X[t - 3]);
@@ -597,20 +611,14 @@ __device__ __forceinline__ void march_stream(const Dev &D, const uint32_t *X, co
                     char *dst = (char *)D.pool + (uint64_t)s3 * (BLK * BS);
                     double nv;
                     if constexpr (ST == VL_F64) {
-                        nv = (double)a3 + (Ff_prev - Ff);
+                        nv = a3d + (Ff_prev - Ff);
                         *(double *)(dst + lane_off) = nv;
                     } else {
-                        const double x = (double)a3 + (Ff_prev - Ff) + carry;
-                        const double xs = fmax(x, 0.0);  // no negative density is stored
-                        if constexpr (ST == VL_F32) {
-                            const float q = (float)xs;
-                            nv = (double)q;
-                            *(float *)(dst + lane_off) = q;
-                        } else {
-                            const uint16_t h = bf16_rne_f64(xs);
-                            nv = (double)bf16_to_f32(h);
-                            *(uint16_t *)(dst + lane_off) = h;
-                        }
+                        const double x = a3d + (Ff_prev - Ff) + carry;
+                        if constexpr (ST == VL_F32)
+                            *(float *)(dst + lane_off) = narrow_f32(x, nv);
+                        else
+                            *(uint16_t *)(dst + lane_off) = narrow_bf16(x, nv);
                         carry = x - nv;
                     }
                     if constexpr (LAST) {
@@ -619,7 +627,7 @@ __device__ __forceinline__ void march_stream(const Dev &D, const uint32_t *X, co
                     }
                 }
             }
-            a3 = a2;
+            a3d = aid;
             a2 = a1;
             a1 = a;
             da_prev = da;
