@@ -288,7 +288,7 @@ def run(p, w, storage, mode, steps, warmup, tune_steps, variant=None, graph_step
     return out
 
 
-def side_run(kind, n, hot, storage, steps, tune_steps, slack=1.3):
+def side_run(kind, n, hot, storage, steps, tune_steps, slack=1.8):
     """A shorter measurement of another workload or storage (for the extras)."""
     import torch
 
@@ -373,7 +373,8 @@ def main():
     log("generated %d blocks (%.3e phase-space cells) in %.1f s; workspace %.1f GB"
         % (w.nblocks, w.nblocks * 64.0, time.time() - t0, p.ws_bytes / 1e9))
     r = run(p, w, storage, mode, args.steps, args.warmup, args.tune_steps, args.variant, gsteps)
-    log("timed %d steps in %.3f s" % (args.steps, r["elapsed"]))
+    log("timed %d steps in %.3f s; kernel ms per step %s" % (
+        args.steps, r["elapsed"], {k: round(v, 2) for k, v in r["kernel_ms_per_step"].items()}))
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0").fill_(1)
         dst = torch.empty_like(src)

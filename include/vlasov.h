@@ -112,7 +112,7 @@ typedef struct vl_step_stats {
     uint64_t device_errors; /* capacity overflow bits recorded on the device (0 = none):
                                1 free local slots, 2 ghost slots, 4 cell list,
                                8 work items, 16 work rows, 32 ghost lists,
-                               64 local lists */
+                               64 local lists, 128 moments scratch */
 } vl_step_stats;
 
 typedef struct vl_partition vl_partition;

@@ -78,6 +78,12 @@ def lib():
         L.vlo_local_mass.argtypes = [C.c_void_p]
         L.vlo_moments.argtypes = [C.c_void_p, f64p, f64p, f64p, f64p]
         L.vlo_ppm_line.argtypes = [f64p, C.c_int, C.c_double, f64p, f64p, f64p, f64p, f64p, f64p]
+        L.vlo_accel_map.argtypes = [f64p, f64p, C.c_double, C.c_double, f64p, f64p]
+        L.vlo_slice_factors.restype = C.c_int
+        L.vlo_slice_factors.argtypes = [f64p, f64p, i32p, f64p]
+        L.vlo_remap_column.argtypes = [f64p, C.c_int, C.c_double, C.c_double, f64p]
+        L.vlo_accelerate.restype = C.c_int
+        L.vlo_accelerate.argtypes = [C.c_void_p, C.c_double, C.c_double, f64p, i32p, f64p]
         _lib = L
     return _lib
 
@@ -94,6 +100,35 @@ def ppm_line(a, c):
                        arrs["flux"])
     arrs["out"] = out
     return arrs
+
+
+def accel_map(E, B, qm, dt):
+    """The exact velocity map of constant fields E, B over dt for charge-to-
+    mass ratio qm: v' = A v + c.  Returns (A (3x3), c (3,))."""
+    A = np.zeros(9)
+    c = np.zeros(3)
+    lib().vlo_accel_map(np.ascontiguousarray(E, np.float64), np.ascontiguousarray(B, np.float64),
+                        float(qm), float(dt), A, c)
+    return A.reshape(3, 3), c
+
+
+def slice_factors(A, c, order=(0, 1, 2)):
+    """The three one-coordinate maps of the SLICE-3D split of v' = A v + c in
+    the given axis order: a (3, 4) array, row k = coefficients of coordinates
+    0..2 and the constant of the map that sets coordinate order[k]; None if a
+    step is not invertible and order-preserving."""
+    M = np.zeros(12)
+    rc = lib().vlo_slice_factors(np.ascontiguousarray(A, np.float64).reshape(-1),
+                                 np.ascontiguousarray(c, np.float64), np.array(order, np.int32), M)
+    return None if rc else M.reshape(3, 4)
+
+
+def remap_column(a, alpha, sigma):
+    """Conservative remap of a column of unit cells under u -> alpha u + sigma."""
+    a = np.ascontiguousarray(a, np.float64)
+    out = np.zeros_like(a)
+    lib().vlo_remap_column(a, a.size, float(alpha), float(sigma), out)
+    return out
 
 
 class OraclePartition:
@@ -213,6 +248,16 @@ class OraclePartition:
             raise RuntimeError("vlo_step: %d" % rc)
         return {"mass_before": st[0], "mass_after": st[1], "pruned_mass": st[2],
                 "updates": (int(st[3]), int(st[4]), int(st[5])), "blocks": int(st[6])}
+
+    def accelerate(self, dt, qm, EB, order=(0, 1, 2)):
+        """One acceleration step of the local cells (fields EB: (ncell, 6) as
+        Ex, Ey, Ez, Bx, By, Bz per cell, x fastest)."""
+        st = np.zeros(4)
+        EB = np.ascontiguousarray(EB, np.float64).reshape(-1)
+        rc = lib().vlo_accelerate(self._h, float(dt), float(qm), EB, np.array(order, np.int32), st)
+        if rc:
+            raise RuntimeError("vlo_accelerate: %d" % rc)
+        return {"mass_before": st[0], "mass_after": st[1], "pruned_mass": st[2], "blocks": int(st[3])}
 
     def step_rc(self, dt, mode=COALESCED):
         st = np.zeros(8)

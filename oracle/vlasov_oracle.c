@@ -763,3 +763,255 @@ void vlo_moments(void *h, double *dens, double *V, double *P, double *total)
             }
     *total = tot;
 }
+
+/* ------------------------------------------------------------------------ */
+/* acceleration: the Lorentz-force term of the Vlasov equation (Section 2,  */
+/* eq. 1) over one time step, as three velocity-axis shears (SLICE-3D,      */
+/* Zerroukat & Allen 2012, which Section 2 names for this solver)           */
+/* ------------------------------------------------------------------------ */
+/*
+ * In fields E, B that are constant over the step, every velocity moves along
+ * its characteristic dv/dt = (q/m)(E + v x B): the part along b = B/|B|
+ * gains (q/m)(E.b) t, the rest gyrates about the E x B drift velocity
+ * vE = E x B / |B|^2 by the angle -(q/m)|B| t.  Over dt this is the affine
+ * map v' = A v + c with A the rotation by theta = -(q/m)|B| dt about b and
+ * c = (I - A) vE + (q/m)(E.b) dt b; with B = 0 it is v' = v + (q/m) E dt.
+ * Rotation about a unit axis b by theta (Rodrigues):
+ *   A = cos(theta) I + sin(theta) [b]x + (1 - cos(theta)) b b^T.
+ */
+void vlo_accel_map(const double *E, const double *B, double qm, double dt, double *A, double *c)
+{
+    double Bm = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    for (int i = 0; i < 9; i++) A[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    if (Bm == 0.0) {
+        for (int d = 0; d < 3; d++) c[d] = qm * E[d] * dt;
+        return;
+    }
+    double b[3] = {B[0] / Bm, B[1] / Bm, B[2] / Bm};
+    double th = -qm * Bm * dt;
+    double co = cos(th), si = sin(th);
+    double cross[9] = {0.0, -b[2], b[1], b[2], 0.0, -b[0], -b[1], b[0], 0.0};
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            A[3 * i + j] = (i == j ? co : 0.0) + si * cross[3 * i + j] + (1.0 - co) * b[i] * b[j];
+    double vE[3] = {(E[1] * B[2] - E[2] * B[1]) / (Bm * Bm), (E[2] * B[0] - E[0] * B[2]) / (Bm * Bm),
+                    (E[0] * B[1] - E[1] * B[0]) / (Bm * Bm)};
+    double Epar = E[0] * b[0] + E[1] * b[1] + E[2] * b[2];
+    for (int i = 0; i < 3; i++) {
+        double Av = A[3 * i] * vE[0] + A[3 * i + 1] * vE[1] + A[3 * i + 2] * vE[2];
+        c[i] = vE[i] - Av + qm * Epar * dt * b[i];
+    }
+}
+
+/*
+ * SLICE-3D splits the map into three maps that each change one velocity
+ * coordinate, in the order o[0], o[1], o[2]: the k-th sets coordinate o[k] to
+ * its final value, written as an affine function of the coordinates the
+ * velocity has after the maps before it.  With the homogeneous 4x4 form T of
+ * the map (rows A | c), step k's row is T's row o[k] times the inverses of the
+ * steps before it, so the three steps compose to T exactly.
+ * M[4k .. 4k+3] receives step k's row (coefficients of coordinates 0, 1, 2 and
+ * the constant).  Returns 0, or -1 if a step's own coefficient is not
+ * positive (the step would not be invertible and order-preserving).
+ */
+static void inv_step(const double *row, int d, double *Minv)
+{
+    /* inverse of the identity with row d replaced by row (4x4, row-major) */
+    for (int i = 0; i < 16; i++) Minv[i] = (i % 5 == 0) ? 1.0 : 0.0;
+    for (int j = 0; j < 4; j++) Minv[4 * d + j] = (j == d) ? 1.0 / row[d] : -row[j] / row[d];
+}
+
+static void row_times(const double *row, const double *M, double *out)
+{
+    for (int j = 0; j < 4; j++) {
+        double s = 0.0;
+        for (int i = 0; i < 4; i++) s += row[i] * M[4 * i + j];
+        out[j] = s;
+    }
+}
+
+int vlo_slice_factors(const double *A, const double *c, const int32_t *o, double *M)
+{
+    double T[3][4];
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) T[i][j] = A[3 * i + j];
+        T[i][3] = c[i];
+    }
+    double r0[4], r1[4], r2[4], t[4], I0[16], I1[16];
+    for (int j = 0; j < 4; j++) r0[j] = T[o[0]][j];
+    if (!(r0[o[0]] > 0.0)) return -1;
+    inv_step(r0, o[0], I0);
+    row_times(T[o[1]], I0, r1);
+    if (!(r1[o[1]] > 0.0)) return -1;
+    inv_step(r1, o[1], I1);
+    row_times(T[o[2]], I0, t);
+    row_times(t, I1, r2);
+    if (!(r2[o[2]] > 0.0)) return -1;
+    for (int j = 0; j < 4; j++) {
+        M[j] = r0[j];
+        M[4 + j] = r1[j];
+        M[8 + j] = r2[j];
+    }
+    return 0;
+}
+
+/*
+ * Conservative remap of one column of N cells of unit width: cell i covers
+ * [i, i+1) and holds the average a[i]; values outside [0, N) are zero.  The
+ * column moves by u -> alpha u + sigma (alpha > 0), so cell i of the result
+ * receives the mass of the source interval [(i - sigma)/alpha,
+ * (i + 1 - sigma)/alpha] under the CW84 parabolas of a (the same slopes,
+ * faces and limiter as the spatial remap), divided by its unit width.  A
+ * source cell covered whole contributes its average exactly.
+ */
+void vlo_remap_column(const double *a, int N, double alpha, double sigma, double *out)
+{
+    int L = N + 6;
+    double pad[L], al[L], ar[L], a6[L], tmp[L];
+    for (int i = 0; i < L; i++) pad[i] = (i >= 3 && i < N + 3) ? a[i - 3] : 0.0;
+    for (int i = 0; i < L; i++) al[i] = ar[i] = a6[i] = 0.0;
+    vlo_ppm_line(pad, L, 0.0, tmp, NULL, al, ar, a6, NULL);
+    for (int i = 0; i < N; i++) {
+        double lo = ((double)i - sigma) / alpha, hi = ((double)i + 1.0 - sigma) / alpha;
+        double m = 0.0;
+        int j0 = (int)floor(lo), j1 = (int)floor(hi);
+        if (j0 < 0) j0 = 0;
+        if (j1 > N - 1) j1 = N - 1;
+        for (int j = j0; j <= j1; j++) {
+            double xa = lo - j, xb = hi - j;
+            if (xa < 0.0) xa = 0.0;
+            if (xb > 1.0) xb = 1.0;
+            if (!(xb > xa)) continue;
+            int q = j + 3;
+            if (xa == 0.0 && xb == 1.0) {
+                m += pad[q];
+                continue;
+            }
+            double dA = ar[q] - al[q];
+            m += al[q] * (xb - xa) + 0.5 * (dA + a6[q]) * (xb * xb - xa * xa) -
+                 a6[q] * (xb * xb * xb - xa * xa * xa) / 3.0;
+        }
+        out[i] = m;
+    }
+}
+
+/*
+ * One acceleration step of every local cell: the fields of cell q are
+ * EB[6q .. 6q+5] = (Ex, Ey, Ez, Bx, By, Bz), qm the charge-to-mass ratio.  The
+ * cell's velocity space is remapped densely (absent blocks read as zero) by
+ * the three steps of vlo_slice_factors in the order o; a column along axis d
+ * (fixed cells of the other two axes, at their centre velocities w) moves by
+ * w_d -> alpha w_d + s with alpha and s from the step's row.  The new block
+ * list is the old list plus every block holding a nonzero value; then the
+ * end-of-step pruning (as after a translation step).  Mass leaving the
+ * velocity mesh is lost.  stats (may be NULL): [0] local mass before,
+ * [1] after, [2] pruned, [3] local blocks after.  Returns 0, or -1 if a
+ * cell's map cannot be split (see vlo_slice_factors).
+ */
+int vlo_accelerate(void *h, double dt, double qm, const double *EB, const int32_t *o, double *stats)
+{
+    vlo_part *p = (vlo_part *)h;
+    const int nv0 = p->nv[0], nv1 = p->nv[1], nv2 = p->nv[2];
+    const int64_t NV = (int64_t)nv0 * nv1 * nv2;
+    const int64_t ncell = (int64_t)p->n[0] * p->n[1] * p->n[2];
+    double m0 = stats ? vlo_local_mass(h) : 0.0;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic) reduction(| : bad)
+    for (int64_t q = 0; q < ncell; q++) {
+        int x = (int)(q % p->n[0]), y = (int)((q / p->n[0]) % p->n[1]), z = (int)(q / ((int64_t)p->n[0] * p->n[1]));
+        vlo_cell *cl = &p->cells[cidx(p, x + VLO_H, y + VLO_H, z + VLO_H)];
+        double A[9], c[3], M[12];
+        vlo_accel_map(EB + 6 * q, EB + 6 * q + 3, qm, dt, A, c);
+        if (vlo_slice_factors(A, c, o, M)) {
+            bad = 1;
+            continue;
+        }
+        /* dense velocity space of the cell, j = j0 + nv0 (j1 + nv1 j2) */
+        double *f = (double *)calloc((size_t)NV, sizeof(double));
+        for (int k = 0; k < cl->n; k++)
+            for (int l = 0; l < VLO_BLK; l++) {
+                int j0 = vel_index(p, 0, cl->ids[k], l), j1 = vel_index(p, 1, cl->ids[k], l),
+                    j2 = vel_index(p, 2, cl->ids[k], l);
+                f[j0 + (int64_t)nv0 * (j1 + (int64_t)nv1 * j2)] = cl->f[(size_t)k * VLO_BLK + l];
+            }
+        const int nv[3] = {nv0, nv1, nv2};
+        const int64_t stride[3] = {1, nv0, (int64_t)nv0 * nv1};
+        int maxn = nv0 > nv1 ? (nv0 > nv2 ? nv0 : nv2) : (nv1 > nv2 ? nv1 : nv2);
+        double *col = (double *)malloc(sizeof(double) * (size_t)maxn);
+        double *res = (double *)malloc(sizeof(double) * (size_t)maxn);
+        for (int k = 0; k < 3; k++) {
+            const int d = o[k];
+            const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
+            const double *row = M + 4 * k;
+            const double alpha = row[d];
+            for (int i2 = 0; i2 < nv[e2]; i2++)
+                for (int i1 = 0; i1 < nv[e1]; i1++) {
+                    double w1 = p->vmin[e1] + ((double)i1 + 0.5) * p->dv[e1];
+                    double w2 = p->vmin[e2] + ((double)i2 + 0.5) * p->dv[e2];
+                    double s = row[e1] * w1 + row[e2] * w2 + row[3];
+                    /* in cell units along d: u -> alpha u + sigma */
+                    double sigma = ((alpha - 1.0) * p->vmin[d] + s) / p->dv[d];
+                    int64_t base = (int64_t)i1 * stride[e1] + (int64_t)i2 * stride[e2];
+                    int any = 0;
+                    for (int i = 0; i < nv[d]; i++) {
+                        col[i] = f[base + (int64_t)i * stride[d]];
+                        any |= col[i] != 0.0;
+                    }
+                    if (!any) continue;
+                    vlo_remap_column(col, nv[d], alpha, sigma, res);
+                    for (int i = 0; i < nv[d]; i++) f[base + (int64_t)i * stride[d]] = res[i];
+                }
+        }
+        free(col);
+        free(res);
+        /* new list: the old blocks and every block holding a nonzero value */
+        char *keep = (char *)calloc((size_t)p->NB, 1);
+        for (int k = 0; k < cl->n; k++) keep[cl->ids[k]] = 1;
+        for (int32_t b = 0; b < p->NB; b++) {
+            if (keep[b]) continue;
+            for (int l = 0; l < VLO_BLK && !keep[b]; l++) {
+                int j0 = vel_index(p, 0, b, l), j1 = vel_index(p, 1, b, l), j2 = vel_index(p, 2, b, l);
+                if (f[j0 + (int64_t)nv0 * (j1 + (int64_t)nv1 * j2)] != 0.0) keep[b] = 1;
+            }
+        }
+        int nn = 0;
+        for (int32_t b = 0; b < p->NB; b++) nn += keep[b];
+        int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nn > 0 ? nn : 1));
+        double *nf = (double *)malloc(sizeof(double) * (size_t)(nn > 0 ? nn : 1) * VLO_BLK);
+        int u = 0;
+        for (int32_t b = 0; b < p->NB; b++)
+            if (keep[b]) {
+                ids[u] = b;
+                for (int l = 0; l < VLO_BLK; l++) {
+                    int j0 = vel_index(p, 0, b, l), j1 = vel_index(p, 1, b, l), j2 = vel_index(p, 2, b, l);
+                    nf[(size_t)u * VLO_BLK + l] = f[j0 + (int64_t)nv0 * (j1 + (int64_t)nv1 * j2)];
+                }
+                u++;
+            }
+        free(keep);
+        free(f);
+        free(cl->ids);
+        free(cl->f);
+        cl->ids = ids;
+        cl->f = nf;
+        cl->n = nn;
+    }
+    if (bad) return -1;
+    double pruned = 0.0, vol = ps_volume(p);
+    int64_t nblocks = 0;
+    for (int z = 0; z < p->n[2]; z++)
+        for (int y = 0; y < p->n[1]; y++)
+            for (int x = 0; x < p->n[0]; x++) {
+                vlo_cell *cl = &p->cells[cidx(p, x + VLO_H, y + VLO_H, z + VLO_H)];
+                pruned += prune_cell(p, cl, vol);
+                nblocks += cl->n;
+            }
+    p->ghosts_valid = 0;
+    if (stats) {
+        stats[0] = m0;
+        stats[1] = vlo_local_mass(h);
+        stats[2] = pruned;
+        stats[3] = (double)nblocks;
+    }
+    return 0;
+}

@@ -23,8 +23,9 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t pool, ring, lstart, lcount, lcapa, lsorted, lid, lslot, litem, rows, items, masks, resid, penfirst,
-        pencnt, pensum, ctl, cover, cellred, red, cellcnt, total;
-    int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap, pen_cap;
+        pencnt, pensum, ctl, cover, cellred, red, cellcnt, mom, total;
+    int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap, pen_cap, mom_parts;
+    int tab_stride;
     int wlmax, cover_stride;
 };
 
@@ -102,6 +103,10 @@ Layout make_layout(const vl_desc *d)
     L.cellred = o; o = align_up(o + (size_t)L.nlocal * 8);
     L.red = o;     o = align_up(o + (size_t)RED_DOUBLES * 8);
     L.cellcnt = o; o = align_up(o + (size_t)L.nlocal * 4);
+    // moments: a split cell has fewer than 2 cnt / MOM_CHUNK chunks
+    L.mom_parts = 2 * lcap / MOM_CHUNK + 64;
+    L.tab_stride = 2 * std::max(d->nblk[0], std::max(d->nblk[1], d->nblk[2])) - 1;
+    L.mom = o;     o = align_up(o + (size_t)moments_scratch_bytes(L.nlocal, L.mom_parts, L.mom_parts, L.tab_stride));
     L.total = o;
     return L;
 }
@@ -144,6 +149,7 @@ struct vl_partition {
     bool bad;
     bool has_cover;
     std::vector<double> cover_host;
+    MomScratch mom;       // moments scratch in the workspace
 };
 
 namespace {
@@ -444,6 +450,7 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
     D.cell_red = (double *)(w + L.cellred);
     D.red = (double *)(w + L.red);
     D.cell_cnt = (int32_t *)(w + L.cellcnt);
+    p->mom = carve_moments_scratch(w + L.mom, L.nlocal, L.mom_parts, L.mom_parts, L.tab_stride, MOM_CHUNK);
 
     // host-side construction of cell metadata and local lists (region 0)
     std::vector<int64_t> lstart(L.N, D.reg_off[2]);
@@ -695,11 +702,11 @@ int vl_moments(vl_partition *p, double *dev_n, double *dev_V3, double *dev_P6, d
     const Dev &D = p->D;
     {
         ProfScope ps(p, K_OTHER);
-        launch_moments(D, dev_n, dev_V3, dev_P6, p->stream);
+        launch_moments(D, p->mom, dev_n, dev_V3, dev_P6, p->stream);
     }
     VL_HIP(hipGetLastError());
     if (host_total_mass) {
-        launch_reduce(D, D.cell_red, D.nlocal, D.red + 5, p->stream);
+        launch_reduce(D, p->mom.cell_mass, D.nlocal, D.red + 5, p->stream);
         VL_HIP(hipMemcpyAsync(host_total_mass, D.red + 5, sizeof(double), hipMemcpyDeviceToHost, p->stream));
         return device_status(p);
     }

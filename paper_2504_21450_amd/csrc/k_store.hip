@@ -332,146 +332,279 @@ void launch_cell_counts(const Dev &D, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// velocity moments, FP64.  One wavefront per local cell, one lane per velocity
-// cell of a block.  Sums are taken about a reference velocity R of the cell
-// (the mean centre of its blocks, which lies within a few thermal speeds of
-// the bulk velocity of the distributions used here), so the pressure tensor
+// velocity moments, FP64 (textbook definitions).  Sums are taken about a
+// reference velocity R of the cell, the centre of the block in the middle of
+// its id-sorted list (within a few thermal speeds of the bulk velocity for
+// the distributions here), so the pressure tensor
 // P = m dv^3 (S2 - S1 S1^T / S0) does not subtract two large raw moments:
 //   S0 = sum f, S1 = sum f (v - R), S2 = sum f (v - R)(v - R)^T.
+// Work units: the first `chunk` blocks of every local cell, and every further
+// chunk of a cell with more blocks (its own unit), so the hot cells of a
+// mixture are spread over many wavefronts.  A unit of a cell with one chunk
+// writes the cell's moments; the units of a split cell leave ten partial sums
+// each, which the cell's combine pass adds in chunk order (the same result in
+// every run).  Per block the lanes add f, f c, f c c^T with c the block
+// centre's offset from R (uniform over the block, read from a small table);
+// each lane's offset o within the block enters once at the end:
+//   sum f (c + o) = S1c + o S0,  sum f (c+o)(c+o)^T = S2c + S1c o^T + o S1c^T + S0 o o^T.
 // ---------------------------------------------------------------------------
-__device__ inline void block_centre(const Dev &D, int32_t b, double &cx, double &cy, double &cz)
+__device__ inline double wave_sum_d(double v)
 {
-    const int bx = b % D.nblk[0], by = (b / D.nblk[0]) % D.nblk[1], bz = b / (D.nblk[0] * D.nblk[1]);
-    cx = D.vmin[0] + (4 * bx + 2) * D.dv[0];
-    cy = D.vmin[1] + (4 * by + 2) * D.dv[1];
-    cz = D.vmin[2] + (4 * bz + 2) * D.dv[2];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// packed block coordinates bx | by << 10 | bz << 20
+__device__ inline int32_t pack_coords(const Dev &D, int32_t id)
+{
+    return (id % D.nblk[0]) | (((id / D.nblk[0]) % D.nblk[1]) << 10) | ((id / (D.nblk[0] * D.nblk[1])) << 20);
+}
+
+// moments of one cell from its sums about R (lane 0 writes)
+__device__ inline void moments_finish(const Dev &D, int64_t q, const double (&S)[10], const double R[3],
+                                      double *dn, double *dV, double *dP, double *cell_mass)
+{
+    const double dv3 = D.dv[0] * D.dv[1] * D.dv[2];
+    const double mp = 1.67262192e-27;
+    const double s0 = S[0];
+    const double nd = dv3 * s0;
+    double u[3] = {0.0, 0.0, 0.0};
+    if (s0 != 0.0)
+        for (int a = 0; a < 3; a++) u[a] = S[1 + a] / s0;
+    if (dn) dn[q] = nd;
+    if (dV)
+        for (int a = 0; a < 3; a++) dV[3 * q + a] = R[a] + u[a];
+    if (dP) {
+        const double k = mp * dv3;
+        dP[6 * q + 0] = k * (S[4] - S[1] * u[0]);
+        dP[6 * q + 1] = k * (S[5] - S[2] * u[1]);
+        dP[6 * q + 2] = k * (S[6] - S[3] * u[2]);
+        dP[6 * q + 3] = k * (S[7] - S[1] * u[1]);
+        dP[6 * q + 4] = k * (S[8] - S[1] * u[2]);
+        dP[6 * q + 5] = k * (S[9] - S[2] * u[2]);
+    }
+    cell_mass[q] = nd * D.dx[0] * D.dx[1] * D.dx[2];
+}
+
+__device__ inline void reference_velocity(const Dev &D, int32_t idR, int cnt, double R[3], int32_t &pkR)
+{
+    pkR = cnt > 0 ? pack_coords(D, idR) : 0;
+    const int b[3] = {pkR & 1023, (pkR >> 10) & 1023, pkR >> 20};
+    for (int a = 0; a < 3; a++) R[a] = cnt > 0 ? D.vmin[a] + (4 * b[a] + 2) * D.dv[a] : 0.0;
+}
+
+// counters to zero (a kernel, not a memset, so graph captures replay it
+// faithfully) and the block-centre offset table
+__global__ __launch_bounds__(256) void k_mom_reset(Dev D, MomScratch M)
+{
+    if (threadIdx.x == 0) {
+        M.ctr[0] = 0ull;
+        M.ctr[1] = 0ull;
+    }
+    const int tmid = (M.tab_stride - 1) / 2;
+    for (int i = threadIdx.x; i < 3 * M.tab_stride; i += 256) {
+        const int a = i / M.tab_stride, k = i % M.tab_stride - tmid;
+        M.tab[i] = (double)(4 * k) * D.dv[a];
+    }
+}
+
+// per local cell: the partial slots of a split cell and its further chunks
+__global__ __launch_bounds__(256) void k_mom_plan(Dev D, MomScratch M)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= D.nlocal || failed(D)) return;
+    int x, y, z;
+    local_coords(D, q, x, y, z);
+    const int cnt = D.lcount[cell_index(D, x + H, y + H, z + H)];
+    const int nch = (cnt + M.chunk - 1) / M.chunk;
+    if (nch <= 1) {
+        M.cell_base[q] = -1;
+        return;
+    }
+    const unsigned long long base = atomicAdd(&M.ctr[0], (unsigned long long)nch);
+    const unsigned long long eb = atomicAdd(&M.ctr[1], (unsigned long long)(nch - 1));
+    if ((int64_t)(base + nch) > M.cap_part || (int64_t)(eb + nch - 1) > M.cap_extra) {
+        atomicOr(&D.ctl->err, (unsigned long long)E_MOMENTS);  // not reached: capacities cover any list
+        M.cell_base[q] = -1;
+        return;
+    }
+    M.cell_base[q] = (int32_t)base;
+    for (int j = 1; j < nch; j++) M.extra[eb + j - 1] = make_int2((int)q, j);
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_moments(Dev D, double *dn, double *dV, double *dP)
+__global__ __launch_bounds__(256) void k_mom_units(Dev D, MomScratch M, double *dn, double *dV, double *dP)
 {
+    if (failed(D)) return;
     const int lane = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nunits = D.nlocal + (int64_t)min(M.ctr[1], (unsigned long long)M.cap_extra);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    using T = typename Storage<ST>::T;
+    constexpr int NF = ST == VL_F64 ? 8 : 16;  // raw words of NF blocks in flight
+    const T *pool = (const T *)D.pool;
+    const int tstride = M.tab_stride;          // offsets table: axis a, k in [-(tstride-1)/2, ..]
+    const int tmid = (tstride - 1) / 2;
+    // the lane's velocity offset from its block's centre
+    const double o[3] = {((lane & 3) - 1.5) * D.dv[0], (((lane >> 2) & 3) - 1.5) * D.dv[1],
+                         ((lane >> 4) - 1.5) * D.dv[2]};
+    for (int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); u < nunits; u += nwaves) {
+        int64_t q;
+        int j;
+        if (u < D.nlocal) {
+            q = u;
+            j = 0;
+        } else {
+            const int2 e = M.extra[u - D.nlocal];
+            q = e.x;
+            j = e.y;
+        }
+        int x, y, z;
+        local_coords(D, q, x, y, z);
+        const int64_t c = cell_index(D, x + H, y + H, z + H);
+        const int cnt = D.lcount[c];
+        const int64_t ls = D.lstart[c];
+        double R[3];
+        int32_t pkR;
+        reference_velocity(D, cnt > 0 ? D.lid[ls + cnt / 2] : 0, cnt, R, pkR);
+        const int b0 = j * M.chunk, b1 = min(cnt, b0 + M.chunk);
+        double s0 = 0.0, s1[3] = {0.0, 0.0, 0.0}, s2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        auto acc = [&](double f, int32_t pk) {
+            // block centre offset from R: uniform, from the table
+            const double cx = M.tab[(pk & 1023) - (pkR & 1023) + tmid];
+            const double cy = M.tab[tstride + ((pk >> 10) & 1023) - ((pkR >> 10) & 1023) + tmid];
+            const double cz = M.tab[2 * tstride + (pk >> 20) - (pkR >> 20) + tmid];
+            const double fx = f * cx, fy = f * cy, fz = f * cz;
+            s0 += f;
+            s1[0] += fx;
+            s1[1] += fy;
+            s1[2] += fz;
+            s2[0] = fma(fx, cx, s2[0]);
+            s2[1] = fma(fy, cy, s2[1]);
+            s2[2] = fma(fz, cz, s2[2]);
+            s2[3] = fma(fx, cy, s2[3]);
+            s2[4] = fma(fx, cz, s2[4]);
+            s2[5] = fma(fy, cz, s2[5]);
+        };
+        for (int g = b0; g < b1; g += 64) {
+            const int ng = min(64, b1 - g);
+            const int32_t myid = lane < ng ? D.lid[ls + g + lane] : 0;
+            const int32_t myslot = lane < ng ? D.lslot[ls + g + lane] : 0;
+            const int32_t mypk = pack_coords(D, myid);
+            int k = 0;
+            for (; k + NF <= ng; k += NF) {
+                T r[NF];
+#pragma unroll
+                for (int i = 0; i < NF; i++) r[i] = pool[(int64_t)__builtin_amdgcn_readlane(myslot, k + i) * BLK + lane];
+#pragma unroll
+                for (int i = 0; i < NF; i++) acc(Storage<ST>::widen(r[i]), __builtin_amdgcn_readlane(mypk, k + i));
+            }
+            for (; k < ng; k++)
+                acc(Storage<ST>::widen(pool[(int64_t)__builtin_amdgcn_readlane(myslot, k) * BLK + lane]),
+                    __builtin_amdgcn_readlane(mypk, k));
+        }
+        // the lane's offset within its block, then the sums over the lanes
+        double S[10];
+        S[0] = s0;
+        for (int a = 0; a < 3; a++) S[1 + a] = s1[a] + o[a] * s0;
+        S[4] = s2[0] + 2.0 * o[0] * s1[0] + o[0] * o[0] * s0;
+        S[5] = s2[1] + 2.0 * o[1] * s1[1] + o[1] * o[1] * s0;
+        S[6] = s2[2] + 2.0 * o[2] * s1[2] + o[2] * o[2] * s0;
+        S[7] = s2[3] + o[0] * s1[1] + o[1] * s1[0] + o[0] * o[1] * s0;
+        S[8] = s2[4] + o[0] * s1[2] + o[2] * s1[0] + o[0] * o[2] * s0;
+        S[9] = s2[5] + o[1] * s1[2] + o[2] * s1[1] + o[1] * o[2] * s0;
+        for (int i = 0; i < 10; i++) S[i] = wave_sum_d(S[i]);
+        const int32_t base = M.cell_base[q];
+        if (base < 0) {
+            if (lane == 0) moments_finish(D, q, S, R, dn, dV, dP, M.cell_mass);
+        } else if (lane < 10) {
+            double v = S[0];
+            for (int i = 1; i < 10; i++) v = (lane == i) ? S[i] : v;
+            M.part[((int64_t)base + j) * 10 + lane] = v;
+        }
+    }
+}
+
+// per split cell: its chunks' partial sums added in chunk order
+__global__ __launch_bounds__(256) void k_mom_combine(Dev D, MomScratch M, double *dn, double *dV, double *dP)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= D.nlocal || failed(D)) return;
+    const int32_t base = M.cell_base[q];
+    if (base < 0) return;
     int x, y, z;
     local_coords(D, q, x, y, z);
     const int64_t c = cell_index(D, x + H, y + H, z + H);
     const int cnt = D.lcount[c];
-    const int64_t ls = D.lstart[c];
-    // reference velocity: mean block centre
-    double rx = 0.0, ry = 0.0, rz = 0.0;
-    for (int e = lane; e < cnt; e += 64) {
-        double cx, cy, cz;
-        block_centre(D, D.lid[ls + e], cx, cy, cz);
-        rx += cx;
-        ry += cy;
-        rz += cz;
-    }
-    rx = wave_sum(rx);
-    ry = wave_sum(ry);
-    rz = wave_sum(rz);
-    if (cnt > 0) {
-        rx /= cnt;
-        ry /= cnt;
-        rz /= cnt;
-    }
-    const double ox = ((lane & 3) - 1.5) * D.dv[0] - rx;
-    const double oy = (((lane >> 2) & 3) - 1.5) * D.dv[1] - ry;
-    const double oz = ((lane >> 4) - 1.5) * D.dv[2] - rz;
-    double s0 = 0.0, s1x = 0.0, s1y = 0.0, s1z = 0.0;
-    double sxx = 0.0, syy = 0.0, szz = 0.0, sxy = 0.0, sxz = 0.0, syz = 0.0;
-    // pk: the block's coordinates packed as bx | by << 10 | bz << 20 (each
-    // lane divides its own id once; the loop only unpacks broadcast words)
-    auto acc = [&](double f, int32_t pk) {
-        const double cx = D.vmin[0] + (4 * (pk & 1023) + 2) * D.dv[0];
-        const double cy = D.vmin[1] + (4 * ((pk >> 10) & 1023) + 2) * D.dv[1];
-        const double cz = D.vmin[2] + (4 * (pk >> 20) + 2) * D.dv[2];
-        const double ux = cx + ox, uy = cy + oy, uz = cz + oz;
-        const double fx = f * ux, fy = f * uy, fz = f * uz;
-        s0 += f;
-        s1x += fx;
-        s1y += fy;
-        s1z += fz;
-        sxx += fx * ux;
-        syy += fy * uy;
-        szz += fz * uz;
-        sxy += fx * uy;
-        sxz += fx * uz;
-        syz += fy * uz;
-    };
-    // ids and slots are read 64 at a time (one per lane) and broadcast from
-    // the lanes, so a block load waits on no other load; the raw storage words
-    // of NF blocks are in flight (more for the narrower types, whose loads
-    // carry fewer bytes) and widened to FP64 only when summed
-    using T = typename Storage<ST>::T;
-    constexpr int NF = ST == VL_F64 ? 8 : 16;
-    const T *pool = (const T *)D.pool;
-    for (int g = 0; g < cnt; g += 64) {
-        const int ng = min(64, cnt - g);
-        const int32_t myid = lane < ng ? D.lid[ls + g + lane] : 0;
-        const int32_t myslot = lane < ng ? D.lslot[ls + g + lane] : 0;
-        const int32_t mypk = (myid % D.nblk[0]) | (((myid / D.nblk[0]) % D.nblk[1]) << 10) |
-                             ((myid / (D.nblk[0] * D.nblk[1])) << 20);
-        int k = 0;
-        for (; k + NF <= ng; k += NF) {
-            T r[NF];
-#pragma unroll
-            for (int j = 0; j < NF; j++)
-                r[j] = pool[(int64_t)__builtin_amdgcn_readlane(myslot, k + j) * BLK + lane];
-#pragma unroll
-            for (int j = 0; j < NF; j++) acc(Storage<ST>::widen(r[j]), __builtin_amdgcn_readlane(mypk, k + j));
-        }
-        for (; k < ng; k++)
-            acc(Storage<ST>::widen(pool[(int64_t)__builtin_amdgcn_readlane(myslot, k) * BLK + lane]),
-                __builtin_amdgcn_readlane(mypk, k));
-    }
-    s0 = wave_sum(s0);
-    s1x = wave_sum(s1x);
-    s1y = wave_sum(s1y);
-    s1z = wave_sum(s1z);
-    sxx = wave_sum(sxx);
-    syy = wave_sum(syy);
-    szz = wave_sum(szz);
-    sxy = wave_sum(sxy);
-    sxz = wave_sum(sxz);
-    syz = wave_sum(syz);
-    if (lane == 0) {
-        const double dv3 = D.dv[0] * D.dv[1] * D.dv[2];
-        const double mp = 1.67262192e-27;
-        const double nd = dv3 * s0;
-        double ux = 0.0, uy = 0.0, uz = 0.0;
-        if (s0 != 0.0) {
-            ux = s1x / s0;
-            uy = s1y / s0;
-            uz = s1z / s0;
-        }
-        if (dn) dn[q] = nd;
-        if (dV) {
-            dV[3 * q + 0] = rx + ux;
-            dV[3 * q + 1] = ry + uy;
-            dV[3 * q + 2] = rz + uz;
-        }
-        if (dP) {
-            const double k = mp * dv3;
-            dP[6 * q + 0] = k * (sxx - s1x * ux);
-            dP[6 * q + 1] = k * (syy - s1y * uy);
-            dP[6 * q + 2] = k * (szz - s1z * uz);
-            dP[6 * q + 3] = k * (sxy - s1x * uy);
-            dP[6 * q + 4] = k * (sxz - s1x * uz);
-            dP[6 * q + 5] = k * (syz - s1y * uz);
-        }
-        D.cell_red[q] = nd * D.dx[0] * D.dx[1] * D.dx[2];
-    }
+    const int nch = (cnt + M.chunk - 1) / M.chunk;
+    double S[10];
+    for (int i = 0; i < 10; i++) S[i] = 0.0;
+    for (int j = 0; j < nch; j++)
+        for (int i = 0; i < 10; i++) S[i] += M.part[((int64_t)base + j) * 10 + i];
+    double R[3];
+    int32_t pkR;
+    reference_velocity(D, D.lid[D.lstart[c] + cnt / 2], cnt, R, pkR);
+    moments_finish(D, q, S, R, dn, dV, dP, M.cell_mass);
 }
 
-void launch_moments(const Dev &D, double *dn, double *dV, double *dP, hipStream_t st)
+template <typename K>
+static unsigned resident_groups(K kernel)
 {
-    dim3 g((unsigned)((D.nlocal + 3) / 4));
-    switch (D.storage) {
-    case VL_F64: hipLaunchKernelGGL(k_moments<VL_F64>, g, dim3(256), 0, st, D, dn, dV, dP); break;
-    case VL_F32: hipLaunchKernelGGL(k_moments<VL_F32>, g, dim3(256), 0, st, D, dn, dV, dP); break;
-    default: hipLaunchKernelGGL(k_moments<VL_BF16>, g, dim3(256), 0, st, D, dn, dV, dP); break;
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 256;
     }
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per < 1) per = 1;
+    return (unsigned)(per * ncu);
+}
+
+template <int ST>
+static void launch_mom_units(const Dev &D, const MomScratch &M, double *dn, double *dV, double *dP, hipStream_t st)
+{
+    static const unsigned g = resident_groups(k_mom_units<ST>);
+    hipLaunchKernelGGL(k_mom_units<ST>, dim3(g), dim3(256), 0, st, D, M, dn, dV, dP);
+}
+
+void launch_moments(const Dev &D, const MomScratch &M, double *dn, double *dV, double *dP, hipStream_t st)
+{
+    if (D.nlocal <= 0) return;
+    const dim3 gc((unsigned)((D.nlocal + 255) / 256));
+    hipLaunchKernelGGL(k_mom_reset, dim3(1), dim3(256), 0, st, D, M);
+    hipLaunchKernelGGL(k_mom_plan, gc, dim3(256), 0, st, D, M);
+    switch (D.storage) {
+    case VL_F64: launch_mom_units<VL_F64>(D, M, dn, dV, dP, st); break;
+    case VL_F32: launch_mom_units<VL_F32>(D, M, dn, dV, dP, st); break;
+    default: launch_mom_units<VL_BF16>(D, M, dn, dV, dP, st); break;
+    }
+    hipLaunchKernelGGL(k_mom_combine, gc, dim3(256), 0, st, D, M, dn, dV, dP);
+}
+
+int64_t moments_scratch_bytes(int64_t nlocal, int64_t parts, int64_t extras, int tab_stride)
+{
+    auto al = [](int64_t v) { return (v + 255) / 256 * 256; };
+    return al(16) + al(nlocal * 4) + al(nlocal * 8) + al(parts * 80) + al(extras * 8) + al((int64_t)tab_stride * 24);
+}
+
+MomScratch carve_moments_scratch(void *base, int64_t nlocal, int64_t parts, int64_t extras, int tab_stride,
+                                 int chunk)
+{
+    auto al = [](int64_t v) { return (v + 255) / 256 * 256; };
+    char *w = (char *)base;
+    MomScratch M;
+    M.ctr = (unsigned long long *)w;          w += al(16);
+    M.cell_base = (int32_t *)w;               w += al(nlocal * 4);
+    M.cell_mass = (double *)w;                w += al(nlocal * 8);
+    M.part = (double *)w;                     w += al(parts * 80);
+    M.extra = (int2 *)w;                      w += al(extras * 8);
+    M.tab = (double *)w;
+    M.cap_part = parts;
+    M.cap_extra = extras;
+    M.chunk = chunk;
+    M.tab_stride = tab_stride;
+    return M;
 }
 
 // gather blocks (by slot) into a dense FP64 array, one wavefront per block

@@ -16,10 +16,12 @@
 //   VL_F64 : everything in FP64.
 //   VL_F32 / VL_BF16 : values are loaded into FP32; slopes, faces and the
 //            limiter run in FP32; the Courant number, flux integral and update
-//            in FP64.  The FP64 update plus the carry is rounded to the
-//            storage type (a negative sum is stored as zero) and the
-//            difference is carried along the pencil into the next updated
-//            cell, so a pencil's mass changes only by its final residual,
+//            in FP64.  The FP64 update of a cell takes the rounding residual
+//            carried along the pencil (of either sign) if it holds at least
+//            that much, else the carry passes it by unchanged, so no cell is
+//            driven negative and positive and negative carries are treated
+//            alike; the sum is rounded to the storage type and the difference
+//            carried on.  A pencil's mass changes only by its final carry,
 //            which the item leaves (summed over its 64 lanes in a fixed order)
 //            for the FP64 mass ledger.
 #include "vl_internal.h"
@@ -65,10 +67,10 @@ __device__ __forceinline__ C clamp_min0(C x, C y)
         return fmax((C)0, fmin(x, y));
 }
 
-// The FP64 update x of a cell (its carry included) in the storage type; a
-// negative sum is stored as zero.  nv receives the stored value in FP64, so
-// the caller carries x - nv on, which keeps the pencil's mass exact whatever
-// the rounding.  BF16: FP64 -> FP32 to nearest, then FP32 -> BF16 to nearest
+// The FP64 update x of a cell (its carry included) in the storage type (a
+// negative sum, which only FP32 reconstruction rounding can leave, is stored
+// as zero).  nv receives the stored value in FP64, so the caller carries
+// x - nv on, which keeps the pencil's mass exact whatever the rounding.  BF16: FP64 -> FP32 to nearest, then FP32 -> BF16 to nearest
 // even by the hardware conversion (two roundings; they differ from one
 // correct rounding only where the FP32 value lands on a BF16 midpoint).
 __device__ __forceinline__ float narrow_f32(double x, double &nv)
@@ -227,12 +229,15 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
                 nv = a3d + (Ff_prev - Ff);
                 *(double *)(dst + lane_off) = nv;
             } else {
-                const double x = a3d + (Ff_prev - Ff) + (live ? carry : 0.0);
+                // the carry goes into the cell only if the cell holds at least as much
+                const double base = a3d + (Ff_prev - Ff);
+                const double cin = (live && fabs(carry) <= base) ? carry : 0.0;
+                const double x = base + cin;
                 if constexpr (ST == VL_F32)
                     *(float *)(dst + lane_off) = narrow_f32(x, nv);
                 else
                     *(uint16_t *)(dst + lane_off) = narrow_bf16(x, nv);
-                if (live) carry = x - nv;
+                if (live) carry = (carry - cin) + (x - nv);
             }
             if constexpr (LAST) {
                 const unsigned long long any = __ballot(nv >= smin);
@@ -314,12 +319,15 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
                         nv = a3d + (Ff_prev - Ff);
                         block_store(dst, lane_off, nv);
                     } else {
-                        const double x = a3d + (Ff_prev - Ff) + carry;
+                        // the carry goes into the cell only if the cell holds at least as much
+                        const double base = a3d + (Ff_prev - Ff);
+                        const double cin = (fabs(carry) <= base) ? carry : 0.0;
+                        const double x = base + cin;
                         if constexpr (ST == VL_F32)
                             block_store(dst, lane_off, narrow_f32(x, nv));
                         else
                             block_store(dst, lane_off, narrow_bf16(x, nv));
-                        carry = x - nv;
+                        carry = (carry - cin) + (x - nv);
                     }
                     if constexpr (LAST) {
                         const unsigned long long any = __ballot(nv >= smin);
@@ -614,12 +622,14 @@ __device__ __forceinline__ void march_stream(const Dev &D, const uint32_t *X, co
                         nv = a3d + (Ff_prev - Ff);
                         *(double *)(dst + lane_off) = nv;
                     } else {
-                        const double x = a3d + (Ff_prev - Ff) + carry;
+                        const double base = a3d + (Ff_prev - Ff);
+                        const double cin = (fabs(carry) <= base) ? carry : 0.0;
+                        const double x = base + cin;
                         if constexpr (ST == VL_F32)
                             *(float *)(dst + lane_off) = narrow_f32(x, nv);
                         else
                             *(uint16_t *)(dst + lane_off) = narrow_bf16(x, nv);
-                        carry = x - nv;
+                        carry = (carry - cin) + (x - nv);
                     }
                     if constexpr (LAST) {
                         const unsigned long long any = __ballot(nv >= smin);

@@ -48,7 +48,7 @@ constexpr int NSINK = 8192;            // sink blocks (>= resident wavefronts)
 // device error bits (Ctl::err)
 enum : unsigned long long {
     E_RING = 1, E_GHOST_SLOTS = 2, E_LIST = 4, E_ITEMS = 8, E_ROWS = 16,
-    E_GHOST_LIST = 32, E_LOCAL_LIST = 64
+    E_GHOST_LIST = 32, E_LOCAL_LIST = 64, E_MOMENTS = 128
 };
 
 struct Ctl {
@@ -190,7 +190,25 @@ void launch_ledger_sum(const Dev &D, int d, const int lo[3], const int hi[3], do
 void launch_prune(const Dev &D, int nxt_region, int last_axis, hipStream_t st);
 void launch_cell_mass(const Dev &D, hipStream_t st);
 void launch_reduce(const Dev &D, const double *in, int64_t n, double *out, hipStream_t st);
-void launch_moments(const Dev &D, double *dn, double *dV, double *dP, hipStream_t st);
+// scratch of the moments: per local cell the first partial slot of a split
+// cell (-1: one chunk) and the cell's mass; per chunk of a split cell ten
+// partial sums; the further chunks (cell, chunk) as work units; two counters
+// and the table of block-centre offsets 4 k dv_a (k in [-tmid, tmid])
+struct MomScratch {
+    unsigned long long *ctr;
+    int32_t *cell_base;
+    double *cell_mass;
+    double *part;
+    int2 *extra;
+    double *tab;
+    int64_t cap_part, cap_extra;
+    int chunk, tab_stride;
+};
+constexpr int MOM_CHUNK = 1024;  // blocks per moments work unit (cells with more are split)
+int64_t moments_scratch_bytes(int64_t nlocal, int64_t parts, int64_t extras, int tab_stride);
+MomScratch carve_moments_scratch(void *base, int64_t nlocal, int64_t parts, int64_t extras, int tab_stride,
+                                 int chunk);
+void launch_moments(const Dev &D, const MomScratch &M, double *dn, double *dV, double *dP, hipStream_t st);
 void launch_cell_counts(const Dev &D, hipStream_t st);
 void launch_gather(const Dev &D, const int32_t *slots, int64_t n, double *out, hipStream_t st);
 
