@@ -62,7 +62,8 @@ enum {
     VL_ERR_CAPACITY = -3,     /* block, list or work-list capacity exceeded */
     VL_ERR_STALE_GHOSTS = -4, /* coalesced step without a ghost update */
     VL_ERR_HIP = -5,          /* a HIP runtime call failed */
-    VL_ERR_STATE = -6         /* partition invalid after an earlier error */
+    VL_ERR_STATE = -6,        /* partition invalid after an earlier error */
+    VL_ERR_SCRATCH = -7       /* vl_moments_static: the fixed scratch array is too small */
 };
 
 /* Partition descriptor (all fields are read by vl_workspace_bytes and
@@ -207,6 +208,24 @@ int vl_graph_step(vl_partition *p, double dt, int32_t mode, int32_t nsteps);
  * host_total_mass: optional; sum n dx dy dz, synchronises if non-NULL. */
 int vl_moments(vl_partition *p, double *dev_n, double *dev_V3, double *dev_P6,
                double *host_total_mass);
+
+/* vl_moments for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid allocation): the same
+ * kernels and outputs, with their scratch (the per-cell chunk table and
+ * masses, the partial sums of cells split over several wavefronts, two
+ * counters) in a fixed device array of 64 MiB that the library holds on every
+ * device it runs on until the process ends; nothing is allocated.  dev_n,
+ * dev_V3, dev_P6 as in vl_moments (any may be NULL); dev_total_mass: optional
+ * device double receiving sum n dx dy dz.  Asynchronous; never synchronises.
+ * The array is shared by all partitions on a device and keeps the last
+ * call's contents (the counters are cleared by each call): calls that
+ * overlap on one device race and give wrong results.  Bit-identical to
+ * vl_moments whenever its split of the cells fits the array (cells are split
+ * into more blocks per wavefront otherwise).
+ * Errors: VL_ERR_SCRATCH (more local cells than the array can describe,
+ * about 5 million), VL_ERR_ARG, VL_ERR_STATE, VL_ERR_HIP. */
+int vl_moments_static(vl_partition *p, double *dev_n, double *dev_V3, double *dev_P6,
+                      double *dev_total_mass);
 
 /* Number of blocks held by the local cells.  Synchronises. */
 int vl_local_block_count(vl_partition *p, int64_t *out);

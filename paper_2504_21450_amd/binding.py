@@ -18,13 +18,14 @@ VL_F64, VL_F32, VL_BF16 = 0, 1, 2
 VL_COALESCED, VL_PER_SWEEP = 0, 1
 VL_OK, VL_ERR_ARG, VL_ERR_CFL, VL_ERR_CAPACITY, VL_ERR_STALE_GHOSTS, VL_ERR_HIP, VL_ERR_STATE = (
     0, -1, -2, -3, -4, -5, -6)
+VL_ERR_SCRATCH = -7
 
 EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_load_values", "vl_fill_ghosts", "vl_fill_ghosts_from", "vl_translate_step",
             "vl_moments", "vl_local_block_count", "vl_export_state", "vl_export_cells",
             "vl_set_courant_override", "vl_counters", "vl_profile_start", "vl_profile_stop",
             "vl_autotune", "vl_set_variant", "vl_set_shear_variants", "vl_get_shear_variants",
             "vl_graph_step", "vl_sync", "vl_destroy",
-            "vl_status_string")
+            "vl_status_string", "vl_moments_static")
 
 
 class VlDesc(C.Structure):
@@ -76,6 +77,8 @@ def load():
     L.vl_translate_step.argtypes = [vp, dbl, i32, C.POINTER(VlStepStats)]
     L.vl_moments.restype = C.c_int
     L.vl_moments.argtypes = [vp, vp, vp, vp, vp]
+    L.vl_moments_static.restype = C.c_int
+    L.vl_moments_static.argtypes = [vp, vp, vp, vp, vp]
     L.vl_local_block_count.restype = C.c_int
     L.vl_local_block_count.argtypes = [vp, C.POINTER(i64)]
     L.vl_export_state.restype = C.c_int
@@ -259,6 +262,20 @@ class Partition:
                                  C.c_void_p(dP.data_ptr()), C.byref(tot) if total else None)
         _check("vl_moments", rc)
         return dn, dV.view(self.ncell, 3), dP.view(self.ncell, 6), tot.value
+
+    def moments_static(self):
+        """vl_moments_static: the moments with their scratch in the library's
+        fixed device array (no allocation in the library); asynchronous.
+        Returns device tensors (n, V, P, total mass)."""
+        t = self.torch
+        dn = t.empty(self.ncell, dtype=t.float64, device=self.device)
+        dV = t.empty(self.ncell * 3, dtype=t.float64, device=self.device)
+        dP = t.empty(self.ncell * 6, dtype=t.float64, device=self.device)
+        dt_ = t.empty(1, dtype=t.float64, device=self.device)
+        rc = self.lib.vl_moments_static(self.h, C.c_void_p(dn.data_ptr()), C.c_void_p(dV.data_ptr()),
+                                        C.c_void_p(dP.data_ptr()), C.c_void_p(dt_.data_ptr()))
+        _check("vl_moments_static", rc)
+        return dn, dV.view(self.ncell, 3), dP.view(self.ncell, 6), dt_
 
     COUNTER_NAMES = ("ring_head", "ring_tail", "ring_limit", "ghost_slots", "ghost_list",
                      "list0", "list1", "items", "rows", "work", "err", "upd0", "upd1", "upd2",

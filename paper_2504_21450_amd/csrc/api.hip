@@ -150,6 +150,7 @@ struct vl_partition {
     bool has_cover;
     std::vector<double> cover_host;
     MomScratch mom;       // moments scratch in the workspace
+    void *mom_static;     // device address of the fixed scratch array (vl_moments_static)
 };
 
 namespace {
@@ -354,6 +355,7 @@ const char *vl_status_string(int s)
     case VL_ERR_STALE_GHOSTS: return "coalesced step without a ghost update since the last step";
     case VL_ERR_HIP: return "HIP runtime error";
     case VL_ERR_STATE: return "partition invalid after an earlier error";
+    case VL_ERR_SCRATCH: return "the partition needs more scratch than the fixed device array of vl_moments_static holds";
     default: return "unknown status";
     }
 }
@@ -451,6 +453,10 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
     D.red = (double *)(w + L.red);
     D.cell_cnt = (int32_t *)(w + L.cellcnt);
     p->mom = carve_moments_scratch(w + L.mom, L.nlocal, L.mom_parts, L.mom_parts, L.tab_stride, MOM_CHUNK);
+    // the fixed scratch array of vl_moments_static on this device (its
+    // address, taken once per device)
+    p->mom_static = nullptr;
+    if (static_moments_scratch(&p->mom_static) != 0) p->mom_static = nullptr;  // vl_moments_static reports it
 
     // host-side construction of cell metadata and local lists (region 0)
     std::vector<int64_t> lstart(L.N, D.reg_off[2]);
@@ -710,6 +716,32 @@ int vl_moments(vl_partition *p, double *dev_n, double *dev_V3, double *dev_P6, d
         VL_HIP(hipMemcpyAsync(host_total_mass, D.red + 5, sizeof(double), hipMemcpyDeviceToHost, p->stream));
         return device_status(p);
     }
+    return VL_OK;
+}
+
+int vl_moments_static(vl_partition *p, double *dev_n, double *dev_V3, double *dev_P6, double *dev_total_mass)
+{
+    if (!p) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    const Dev &D = p->D;
+    const Layout &L = p->lay;
+    if (!p->mom_static) return VL_ERR_HIP;
+    // the chunk size that keeps every possible split within the array: the
+    // workspace's when it fits, else larger
+    const int64_t fixed = moments_scratch_bytes(L.nlocal, 0, 0, L.tab_stride);
+    const int64_t per_part = 80 + 8;
+    if (fixed + 64 * per_part + 1024 > STATIC_MOMENTS_SCRATCH_BYTES) return VL_ERR_SCRATCH;
+    const int64_t parts = (STATIC_MOMENTS_SCRATCH_BYTES - fixed - 1024) / per_part;
+    int64_t chunk = MOM_CHUNK;
+    if (2 * D.lcap / chunk + 64 > parts) chunk = (2 * D.lcap + parts - 65) / (parts - 64);
+    if (chunk > (int64_t)1 << 30) return VL_ERR_SCRATCH;
+    const MomScratch M = carve_moments_scratch(p->mom_static, L.nlocal, parts, parts, L.tab_stride, (int)chunk);
+    {
+        ProfScope ps(p, K_OTHER);
+        launch_moments(D, M, dev_n, dev_V3, dev_P6, p->stream);
+        if (dev_total_mass) launch_reduce(D, M.cell_mass, D.nlocal, dev_total_mass, p->stream);
+    }
+    VL_HIP(hipGetLastError());
     return VL_OK;
 }
 

@@ -2,6 +2,7 @@
 // image copy of block lists and payloads), per-cell mass, deterministic
 // reductions and the FP64 velocity moments.
 #include <algorithm>
+#include <mutex>
 
 #include "vl_internal.h"
 #include "vl_storage.h"
@@ -580,6 +581,31 @@ void launch_moments(const Dev &D, const MomScratch &M, double *dn, double *dV, d
     default: launch_mom_units<VL_BF16>(D, M, dn, dV, dP, st); break;
     }
     hipLaunchKernelGGL(k_mom_combine, gc, dim3(256), 0, st, D, M, dn, dV, dP);
+}
+
+// ---------------------------------------------------------------------------
+// the allocation-free moments entry point's scratch: a fixed array in device
+// memory (one per device the library runs on, held until the process ends).
+// Host code never passes the array's name to a kernel: it takes the array's
+// device address once per device with hipGetSymbolAddress and passes that.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[STATIC_MOMENTS_SCRATCH_BYTES];
+
+int static_moments_scratch(void **ptr)
+{
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static void *addr[MAXDEV] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) return -1;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *a = nullptr;
+        if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || !a) return -1;
+        addr[dev] = a;
+    }
+    *ptr = addr[dev];
+    return 0;
 }
 
 int64_t moments_scratch_bytes(int64_t nlocal, int64_t parts, int64_t extras, int tab_stride)

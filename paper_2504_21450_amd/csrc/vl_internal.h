@@ -209,6 +209,10 @@ int64_t moments_scratch_bytes(int64_t nlocal, int64_t parts, int64_t extras, int
 MomScratch carve_moments_scratch(void *base, int64_t nlocal, int64_t parts, int64_t extras, int tab_stride,
                                  int chunk);
 void launch_moments(const Dev &D, const MomScratch &M, double *dn, double *dV, double *dP, hipStream_t st);
+// the fixed device array of the allocation-free moments entry point: its
+// address on the current device (taken once per device), and its size
+int static_moments_scratch(void **ptr);
+constexpr int64_t STATIC_MOMENTS_SCRATCH_BYTES = 64ll << 20;
 void launch_cell_counts(const Dev &D, hipStream_t st);
 void launch_gather(const Dev &D, const int32_t *slots, int64_t n, double *out, hipStream_t st);
 
