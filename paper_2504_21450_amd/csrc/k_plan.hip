@@ -461,34 +461,45 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
             }
         }
         // the new list entries, per cell in ascending block id (the same order
-        // in every run): the slot of the block of chunk rank k new in cell i is
-        // the one the row above took, number s_np[k] + (rank of i among k's
-        // new cells) of this chunk's allocation
-        for (int i = tid; i < L; i += 256) {
-            int want = s_req[i];
+        // in every run): a wavefront per cell tests 64 chunk ranks at a time
+        // and places the cell's new blocks in rank order; the slot of the
+        // block of chunk rank k new in cell i is the one the row above took,
+        // number s_np[k] + (rank of i among k's new cells) of this chunk's
+        // allocation
+        for (int i = wave; i < L; i += 4) {
+            const int want = s_req[i];
             if (want == 0) continue;
-            s_req[i] = 0;
-            if (alloc_failed) continue;
+            const int have = s_new[i];
             const int iw = i >> 5;
             const uint32_t ibit = 1u << (i & 31);
-            for (int k = 0; k < rn && want > 0; k++) {
-                const uint32_t nw = s_newb[k * WL + iw];
-                if (!(nw & ibit)) continue;
-                want--;
-                int qn = s_np[k];
-                for (int w2 = 0; w2 < iw; w2++) qn += popc(s_newb[k * WL + w2]);
-                qn += popc(nw & (ibit - 1u));
-                const int64_t slot = local_pencil ? (int64_t)D.ring[(int64_t)((nb + qn) % (unsigned long long)D.lcap)]
-                                                  : D.lcap + (int64_t)nb + qn;
-                const int lp = s_new[i]++;
-                if (s_cnt[i] + lp < s_cap[i]) {
-                    const int64_t at = s_cs[i] + s_cnt[i] + lp;
-                    D.lid[at] = s_id[k];
-                    D.lslot[at] = (int32_t)slot;
-                    if (last) __builtin_nontemporal_store((int32_t)(ibp + r0 + k), &D.litem[at]);
-                } else {
-                    atomicOr(&D.ctl->err, (unsigned long long)E_LIST);
+            int done = 0;
+            for (int k0 = 0; k0 < rn && done < want && !alloc_failed; k0 += 64) {
+                const int k = k0 + lane;
+                const uint32_t nw = (k < rn) ? s_newb[k * WL + iw] : 0u;
+                const bool is_new = (nw & ibit) != 0u;
+                const unsigned long long bal = __ballot(is_new);
+                if (is_new) {
+                    int qn = s_np[k];
+                    for (int w2 = 0; w2 < iw; w2++) qn += popc(s_newb[k * WL + w2]);
+                    qn += popc(nw & (ibit - 1u));
+                    const int64_t slot = local_pencil
+                                             ? (int64_t)D.ring[(int64_t)((nb + qn) % (unsigned long long)D.lcap)]
+                                             : D.lcap + (int64_t)nb + qn;
+                    const int lp = have + done + (int)__popcll(bal & ((1ull << lane) - 1ull));
+                    if (s_cnt[i] + lp < s_cap[i]) {
+                        const int64_t at = s_cs[i] + s_cnt[i] + lp;
+                        D.lid[at] = s_id[k];
+                        D.lslot[at] = (int32_t)slot;
+                        if (last) __builtin_nontemporal_store((int32_t)(ibp + r0 + k), &D.litem[at]);
+                    } else {
+                        atomicOr(&D.ctl->err, (unsigned long long)E_LIST);
+                    }
                 }
+                done += (int)__popcll(bal);
+            }
+            if (lane == 0) {
+                s_req[i] = 0;
+                if (!alloc_failed) s_new[i] = have + done;
             }
         }
         // rows of the blocks already held: the chunk's run of each list

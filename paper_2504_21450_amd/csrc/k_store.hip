@@ -434,10 +434,14 @@ __global__ __launch_bounds__(256) void k_mom_plan(Dev D, MomScratch M)
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_mom_units(Dev D, MomScratch M, double *dn, double *dV, double *dP)
+__global__ __launch_bounds__(256) void k_mom_units(Dev D, MomScratch M, const double *__restrict__ tab,
+                                                   double *dn, double *dV, double *dP)
 {
     if (failed(D)) return;
     const int lane = threadIdx.x & 63;
+    // the wavefront's index, made visibly uniform so the unit's cell, its
+    // metadata and the offset table are read with scalar loads
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nunits = D.nlocal + (int64_t)min(M.ctr[1], (unsigned long long)M.cap_extra);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     using T = typename Storage<ST>::T;
@@ -448,7 +452,7 @@ __global__ __launch_bounds__(256) void k_mom_units(Dev D, MomScratch M, double *
     // the lane's velocity offset from its block's centre
     const double o[3] = {((lane & 3) - 1.5) * D.dv[0], (((lane >> 2) & 3) - 1.5) * D.dv[1],
                          ((lane >> 4) - 1.5) * D.dv[2]};
-    for (int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); u < nunits; u += nwaves) {
+    for (int64_t u = (int64_t)blockIdx.x * 4 + wv; u < nunits; u += nwaves) {
         int64_t q;
         int j;
         if (u < D.nlocal) {
@@ -456,24 +460,25 @@ __global__ __launch_bounds__(256) void k_mom_units(Dev D, MomScratch M, double *
             j = 0;
         } else {
             const int2 e = M.extra[u - D.nlocal];
-            q = e.x;
-            j = e.y;
+            q = __builtin_amdgcn_readfirstlane(e.x);
+            j = __builtin_amdgcn_readfirstlane(e.y);
         }
         int x, y, z;
         local_coords(D, q, x, y, z);
         const int64_t c = cell_index(D, x + H, y + H, z + H);
-        const int cnt = D.lcount[c];
+        const int cnt = __builtin_amdgcn_readfirstlane(D.lcount[c]);
         const int64_t ls = D.lstart[c];
         double R[3];
         int32_t pkR;
-        reference_velocity(D, cnt > 0 ? D.lid[ls + cnt / 2] : 0, cnt, R, pkR);
+        reference_velocity(D, cnt > 0 ? __builtin_amdgcn_readfirstlane(D.lid[ls + cnt / 2]) : 0, cnt, R, pkR);
+        pkR = __builtin_amdgcn_readfirstlane(pkR);
         const int b0 = j * M.chunk, b1 = min(cnt, b0 + M.chunk);
         double s0 = 0.0, s1[3] = {0.0, 0.0, 0.0}, s2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         auto acc = [&](double f, int32_t pk) {
             // block centre offset from R: uniform, from the table
-            const double cx = M.tab[(pk & 1023) - (pkR & 1023) + tmid];
-            const double cy = M.tab[tstride + ((pk >> 10) & 1023) - ((pkR >> 10) & 1023) + tmid];
-            const double cz = M.tab[2 * tstride + (pk >> 20) - (pkR >> 20) + tmid];
+            const double cx = tab[(pk & 1023) - (pkR & 1023) + tmid];
+            const double cy = tab[tstride + ((pk >> 10) & 1023) - ((pkR >> 10) & 1023) + tmid];
+            const double cz = tab[2 * tstride + (pk >> 20) - (pkR >> 20) + tmid];
             const double fx = f * cx, fy = f * cy, fz = f * cz;
             s0 += f;
             s1[0] += fx;
@@ -566,7 +571,7 @@ template <int ST>
 static void launch_mom_units(const Dev &D, const MomScratch &M, double *dn, double *dV, double *dP, hipStream_t st)
 {
     static const unsigned g = resident_groups(k_mom_units<ST>);
-    hipLaunchKernelGGL(k_mom_units<ST>, dim3(g), dim3(256), 0, st, D, M, dn, dV, dP);
+    hipLaunchKernelGGL(k_mom_units<ST>, dim3(g), dim3(256), 0, st, D, M, (const double *)M.tab, dn, dV, dP);
 }
 
 void launch_moments(const Dev &D, const MomScratch &M, double *dn, double *dV, double *dP, hipStream_t st)
