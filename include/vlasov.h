@@ -104,8 +104,15 @@ typedef struct vl_step_stats {
     double mass_before;   /* local mass before the step */
     double mass_after;    /* local mass held in f after the step */
     double pruned_mass;   /* mass of the blocks removed by pruning */
-    double ledger_mass;   /* FP32/BF16 storage: FP64 rounding residual kept outside
-                             f (0 for FP64) */
+    double ledger_mass;   /* FP32/BF16 storage: change of the FP64 rounding residual
+                             kept outside f in this step (0 for FP64).  Each shear
+                             carries the rounding residual along a pencil line; the
+                             line's final residual, per velocity block, is kept in
+                             FP64 and put back into that line and block at the next
+                             shear along the same axis (spread evenly over its 64
+                             cells), so mass_before = mass_after + pruned_mass +
+                             ledger_mass up to FP64 rounding, and the residual held
+                             outside f stays that of the last shear of each axis */
     int64_t local_blocks; /* blocks held by local cells after the step */
     int64_t updated_ps[3];/* phase-space cells written by each shear (sweep order) */
     int64_t read_ps[3];   /* phase-space cells read by each shear */
@@ -178,8 +185,10 @@ int vl_fill_ghosts_from(vl_partition *p, vl_partition *const *nbr);
  *   mode VL_PER_SWEEP: classical per-direction ghost refresh (Fig. 1), from
  *        the sources of the last vl_fill_ghosts_from if there was one
  *        (required when desc.edges is set), else from periodic images.
- * Both modes give the same local result bit for bit.  The ghost domain is
- * stale afterwards.  dt > 0 [s].  stats: optional host output; if non-NULL
+ * Both modes give the same local result bit for bit (in FP32/BF16 storage
+ * for a partition that stays in one mode: a coalesced step also carries the
+ * rounding residuals of the ghost lines it translates, which a per-sweep step
+ * does not translate).  The ghost domain is stale afterwards.  dt > 0 [s].  stats: optional host output; if non-NULL
  * the call synchronises and also reports device-side errors.
  * Errors: VL_ERR_ARG, VL_ERR_CFL (checked on the host before launch),
  * VL_ERR_STALE_GHOSTS, VL_ERR_CAPACITY (with stats), VL_ERR_STATE, VL_ERR_HIP. */

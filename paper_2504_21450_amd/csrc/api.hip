@@ -23,8 +23,9 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t pool, ring, lstart, lcount, lcapa, lsorted, lid, lslot, litem, rows, items, masks, resid, penfirst,
-        pencnt, pensum, ctl, cover, cellred, red, cellcnt, mom, total;
-    int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap, pen_cap, mom_parts;
+        pencnt, pensum, ctl, cover, cellred, red, cellcnt, mom, lg_ids[4], lg_res[4], lg_kfirst[4],
+        lg_kcnt[4], lg_src, total;
+    int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap, pen_cap, mom_parts, lg_cap;
     int tab_stride;
     int wlmax, cover_stride;
 };
@@ -107,6 +108,17 @@ Layout make_layout(const vl_desc *d)
     L.mom_parts = 2 * lcap / MOM_CHUNK + 64;
     L.tab_stride = 2 * std::max(d->nblk[0], std::max(d->nblk[1], d->nblk[2])) - 1;
     L.mom = o;     o = align_up(o + (size_t)moments_scratch_bytes(L.nlocal, L.mom_parts, L.mom_parts, L.tab_stride));
+    // per-line mass ledger (reduced storage): three stores, one per shear
+    // axis, and a fourth that the next shear writes; each holds a shear's
+    // items (block id and FP64 residual) and per pencil key its item range
+    L.lg_cap = d->storage == VL_F64 ? 0 : L.item_cap;
+    for (int k = 0; k < 4; k++) {
+        L.lg_ids[k] = o;    o = align_up(o + (size_t)L.lg_cap * 4);
+        L.lg_res[k] = o;    o = align_up(o + (size_t)L.lg_cap * 8);
+        L.lg_kfirst[k] = o; o = align_up(o + (size_t)(L.lg_cap ? L.pen_cap : 0) * 4);
+        L.lg_kcnt[k] = o;   o = align_up(o + (size_t)(L.lg_cap ? L.pen_cap : 0) * 4);
+    }
+    L.lg_src = o;  o = align_up(o + (size_t)L.lg_cap * 4);
     L.total = o;
     return L;
 }
@@ -121,15 +133,25 @@ struct Prof {
 };
 
 // Executable graphs of one whole step (coalesced fill when the mode has one,
-// then the translation kernels), one per starting list region.  They hold
+// then the translation kernels), one per starting list region and ledger
+// store rotation (the stores a step reads and writes).  They hold
 // dt, the mode, the shear variant and the Courant table pointer as launch
 // arguments, so any change of these drops them.
 struct GraphCache {
     hipStream_t cap = nullptr;  // private stream, used only to record captures
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[8] = {};  // by starting list region + 2 x ledger rotation phase
     double dt = 0.0;
     int mode = -1;
     int variant[3] = {-1, -1, -1};
+};
+
+// Ledger store rotation: store axis[a] holds the residuals of the last shear
+// along axis a; a shear along a writes store `spare` and then the two swap.
+// A step makes three swaps, so the assignment repeats every four steps.
+struct LedgerRot {
+    int axis[3] = {0, 1, 2};
+    int spare = 3;
+    int phase = 0;  // steps mod 4 (0 without a ledger)
 };
 
 struct vl_partition {
@@ -151,6 +173,8 @@ struct vl_partition {
     std::vector<double> cover_host;
     MomScratch mom;       // moments scratch in the workspace
     void *mom_static;     // device address of the fixed scratch array (vl_moments_static)
+    LedgerStore lgs[4];   // per-line ledger stores (reduced storage)
+    LedgerRot rot;        // which store holds each axis's residuals
 };
 
 namespace {
@@ -232,15 +256,27 @@ void update_box(const vl_partition *p, int mode, int s, int lo[3], int hi[3])
         }
 }
 
+// the ledger stores after one step from `r`
+void rotate(LedgerRot &r, const int order[3], bool on)
+{
+    if (!on) return;
+    for (int s = 0; s < 3; s++) std::swap(r.axis[order[s]], r.spare);
+    r.phase = (r.phase + 1) & 3;
+}
+
 // The kernels of one translation step (growth, work list and shear per axis,
 // then pruning into the other local list region), enqueued on st with no
 // host read-back, so that the sequence can also be captured into a graph.
-// ledger3 (device, optional): the FP64 rounding residuals that each shear
-// leaves outside f on the local pencils, one sum per shear.
+// The ledger stores are those of p->rot, which the caller advances (rotate)
+// once the step is enqueued or launched.
+// ledger3 (device, optional): the change of the FP64 rounding residuals that
+// each shear leaves outside f on the local pencils, one sum per shear.
 void enqueue_translate(vl_partition *p, double dt, int mode, double *ledger3, hipStream_t st)
 {
     const Dev &D = p->D;
     const int nxt = 1 - p->cur;
+    const bool ledger = p->lay.lg_cap > 0;
+    LedgerRot rot = p->rot;
     p->loadable = false;
     launch_book(D, BOOK_STEP_RESET, st);
     for (int s = 0; s < 3; s++) {
@@ -263,13 +299,22 @@ void enqueue_translate(vl_partition *p, double dt, int mode, double *ledger3, hi
                 launch_fill(D, flo, fhi, st);
         }
         launch_book(D, BOOK_SWEEP_RESET, st);
+        LedgerIO lg{};
+        if (ledger) {
+            lg.old = p->lgs[rot.axis[d]];
+            lg.nw = p->lgs[rot.spare];
+            lg.src = (int32_t *)(p->ws + p->lay.lg_src);
+            lg.cap = p->lay.lg_cap;
+            std::swap(rot.axis[d], rot.spare);
+        }
         {
             ProfScope ps(p, K_PLAN);
-            launch_plan(D, d, s, lo, hi, dt, p->cur, st);
+            if (ledger) launch_zero_i32(lg.nw.kcnt, p->lay.pen_cap, st);
+            launch_plan(D, d, s, lo, hi, dt, p->cur, lg, st);
         }
         {
             ProfScope ps(p, K_SHEAR0 + s);
-            launch_sweep(D, d, s, lo, hi, dt, s == 2, st);
+            launch_sweep(D, d, s, lo, hi, dt, s == 2, lg, st);
         }
         if (ledger3) launch_ledger_sum(D, d, lo, hi, ledger3 + s, st);
     }
@@ -305,7 +350,8 @@ void drop_graphs(vl_partition *p)
     for (int &v : g.variant) v = -1;
 }
 
-// Record the step that starts from list region p->cur into g.exec[p->cur].
+// Record the step that starts from list region p->cur and ledger rotation
+// p->rot into its slot of g.exec.
 int capture_step(vl_partition *p, double dt, int mode)
 {
     GraphCache &g = p->graph;
@@ -331,7 +377,7 @@ int capture_step(vl_partition *p, double dt, int mode)
         fprintf(stderr, "libvlasov: graph instantiation failed: %s\n", hipGetErrorString(ie));
         return VL_ERR_HIP;
     }
-    g.exec[p->cur] = exec;
+    g.exec[p->cur + 2 * p->rot.phase] = exec;
     return VL_OK;
 }
 
@@ -452,6 +498,14 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
     D.cell_red = (double *)(w + L.cellred);
     D.red = (double *)(w + L.red);
     D.cell_cnt = (int32_t *)(w + L.cellcnt);
+    for (int k = 0; k < 4; k++) {
+        LedgerStore &g = p->lgs[k];
+        const bool on = L.lg_cap > 0;
+        g.ids = on ? (int32_t *)(w + L.lg_ids[k]) : nullptr;
+        g.res = on ? (double *)(w + L.lg_res[k]) : nullptr;
+        g.kfirst = on ? (int32_t *)(w + L.lg_kfirst[k]) : nullptr;
+        g.kcnt = on ? (int32_t *)(w + L.lg_kcnt[k]) : nullptr;
+    }
     p->mom = carve_moments_scratch(w + L.mom, L.nlocal, L.mom_parts, L.mom_parts, L.tab_stride, MOM_CHUNK);
     // the fixed scratch array of vl_moments_static on this device (its
     // address, taken once per device)
@@ -501,6 +555,12 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
         if (!lid.empty()) {
             if (hipMemcpy(D.lid, lid.data(), lid.size() * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
             if (hipMemcpy(D.lslot, lslot.data(), lslot.size() * 4, hipMemcpyHostToDevice) != hipSuccess) { rc = VL_ERR_HIP; break; }
+        }
+        // empty ledger stores: no line has a residual yet
+        if (L.lg_cap > 0) {
+            bool ok = true;
+            for (int k = 0; k < 4 && ok; k++) ok = hipMemset(p->lgs[k].kcnt, 0, (size_t)L.pen_cap * 4) == hipSuccess;
+            if (!ok) { rc = VL_ERR_HIP; break; }
         }
         // the scratch block reads as zero in the shears
         if (hipMemset((char *)D.pool + (size_t)D.trash * BLK * storage_bytes(d->storage), 0,
@@ -633,6 +693,7 @@ int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *s
     const int nxt = 1 - p->cur;
     VL_HIP(hipGetLastError());
     p->cur = nxt;
+    rotate(p->rot, p->desc.order, p->lay.lg_cap > 0);
     p->ghosts_valid = false;
     if (stats) {
         launch_reduce(D, D.cell_red, D.nlocal, D.red + 2, st);  // pruned mass
@@ -687,15 +748,17 @@ int vl_graph_step(vl_partition *p, double dt, int32_t mode, int32_t nsteps)
         for (int s = 0; s < 3; s++) g.variant[s] = sv[s];
     }
     for (int k = 0; k < nsteps; k++) {
-        if (!g.exec[p->cur]) {
+        const int gi = p->cur + 2 * p->rot.phase;
+        if (!g.exec[gi]) {
             int rc = capture_step(p, dt, mode);
             if (rc) {
                 drop_graphs(p);
                 return rc;
             }
         }
-        VL_HIP(hipGraphLaunch(g.exec[p->cur], p->stream));
+        VL_HIP(hipGraphLaunch(g.exec[gi], p->stream));
         p->cur = 1 - p->cur;
+        rotate(p->rot, p->desc.order, p->lay.lg_cap > 0);
         p->ghosts_valid = false;
     }
     return VL_OK;

@@ -14,9 +14,15 @@
 //      item; in the last shear of a step it also records, per list entry of
 //      the pencil's cells, the item of the entry's block (where the shear
 //      leaves the content flags that the pruning reads).
+//   5. in the reduced storage types, records the pencil's items in the
+//      axis's new ledger store and maps each of them to the item of the same
+//      block in the store of the previous shear along the axis (a bitmap
+//      look-up per old item), so the shear can take that line's residual.
 // Each cell belongs to exactly one pencil of a shear, so the workgroup owns the
 // lists it grows.  Block ids of a chunk of the union are processed at a time
 // so the LDS footprint is bounded.
+#include <algorithm>
+
 #include "vl_internal.h"
 
 namespace vl {
@@ -29,7 +35,9 @@ struct PlanParams {
     int ulo, uhi;        // updated cells along d
     int R;               // chunk capacity (block ids per chunk)
     int cur;             // local list region in use
+    int kstride;         // pencil key of (t1, t2): t1 + kstride t2
     double dt;
+    LedgerIO lg;
 };
 
 __device__ inline int popc(uint32_t v) { return __popc(v); }
@@ -182,6 +190,15 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         if (p < D.pen_cap) {
             D.pen_first[p] = (int64_t)ib;
             D.pen_cnt[p] = U;
+        }
+        if (pp.lg.src) {  // the pencil in the new ledger store (its count was cleared)
+            if ((int64_t)(ib + U) > pp.lg.cap) {
+                atomicOr(&D.ctl->err, (unsigned long long)E_ITEMS);
+            } else {
+                const int key = t1 + pp.kstride * t2;
+                pp.lg.nw.kfirst[key] = (int32_t)ib;
+                pp.lg.nw.kcnt[key] = U;
+            }
         }
     }
     __syncthreads();
@@ -414,6 +431,10 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         // items and new blocks
         for (int k = tid; k < rn; k += 256) {
             const int64_t it = ibp + r0 + k;
+            if (pp.lg.src && it < pp.lg.cap) {  // no old residual unless matched below
+                pp.lg.nw.ids[it] = s_id[k];
+                pp.lg.src[it] = -1;
+            }
             if (s_ai[k + 1] == s_ai[k]) {  // no updated cell holds the block: empty item
                 if (it < D.item_cap) {
                     Item item;
@@ -580,6 +601,24 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         __syncthreads();
     }
 
+    // the line's residuals of the last shear along d: an old item whose block
+    // is in the union gives its index to the item of that block (the union
+    // bitmap and ranks still hold; the -1 entries above were written before
+    // the last barrier of the chunk loop)
+    if (pp.lg.src) {
+        const int key = t1 + pp.kstride * t2;
+        const int ocnt = pp.lg.old.kcnt[key];
+        const int64_t ofirst = pp.lg.old.kfirst[key];
+        for (int j = tid; j < ocnt; j += 256) {
+            const int32_t b = pp.lg.old.ids[ofirst + j];
+            const uint32_t w = s_bm[b >> 5];
+            if ((w >> (b & 31)) & 1u) {
+                const int64_t it = ibp + s_rank[b >> 5] + popc(w & ((1u << (b & 31)) - 1u));
+                if (it < pp.lg.cap) pp.lg.src[it] = (int32_t)(ofirst + j);
+            }
+        }
+    }
+
     // commit list growth
     for (int i = tid; i < L; i += 256) {
         const int a = s_new[i];
@@ -606,11 +645,24 @@ size_t plan_lds_bytes(int W, int R, int WL, int L)
     return b + 64;
 }
 
+__global__ __launch_bounds__(256) void k_zero_i32(int32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
+}
+
+void launch_zero_i32(int32_t *p, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return;
+    const int64_t g = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)g), dim3(256), 0, st, p, n);
+}
+
 void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, int cur,
-                 hipStream_t st)
+                 const LedgerIO &lg, hipStream_t st)
 {
     PlanParams pp;
     pp.cur = cur;
+    pp.lg = lg;
     pp.d = d;
     pp.sidx = sidx;
     pp.e1 = (d == 0) ? 1 : 0;
@@ -621,6 +673,7 @@ void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3]
     pp.n2 = hi[pp.e2] - lo[pp.e2];
     pp.L = D.P[d];
     pp.WL = (pp.L + 31) / 32;
+    pp.kstride = D.P[pp.e1];
     pp.ulo = lo[d];
     pp.uhi = hi[d];
     pp.dt = dt;

@@ -21,9 +21,15 @@
 //            that much, else the carry passes it by unchanged, so no cell is
 //            driven negative and positive and negative carries are treated
 //            alike; the sum is rounded to the storage type and the difference
-//            carried on.  A pencil's mass changes only by its final carry,
-//            which the item leaves (summed over its 64 lanes in a fixed order)
-//            for the FP64 mass ledger.
+//            carried on.  A line's carry starts from the residual its last
+//            shear along the same axis left for the block (its sum over the
+//            block's 64 velocity cells, kept in FP64 in the axis's ledger
+//            store and spread evenly over the lanes) and its final carry,
+//            summed over the lanes in a fixed order, is stored there for the
+//            next one, so residuals are put back into f rather than
+//            accumulating.  The line's stored mass changes only by its final
+//            carry minus its starting one, which the item leaves for the FP64
+//            mass ledger.
 #include "vl_internal.h"
 #include "vl_storage.h"
 
@@ -34,6 +40,10 @@ struct SweepParams {
     int e1, e2, lo1, n1, lo2;  // pencil geometry (to tell local pencils)
     double dt;
     double sparse_min;
+    const double *lg_old;    // residuals of the last shear along d, per old item
+    double *lg_new;          // this shear's, per item
+    const int32_t *lg_src;   // per item: its old item or -1
+    int64_t lg_cap;          // items of a ledger store (0: no ledger)
 };
 
 __device__ inline void wave_sync_lds()
@@ -53,6 +63,48 @@ __device__ __forceinline__ double wave_sum64(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
+}
+
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// The starting carry of each velocity cell of item `it`'s line: 1/64 of the
+// residual the last shear along the axis left for the same line and block (0
+// if the block was not on the line then).  The 64 equal shares add up to the
+// residual exactly; it is returned in `sum` (uniform, in scalar registers).
+template <int ST>
+__device__ __forceinline__ double take_residual(const SweepParams &sp, int64_t it, double &sum)
+{
+    double r = 0.0;
+    if constexpr (ST != VL_F64) {
+        if (it < sp.lg_cap) {
+            const int32_t s = (int32_t)uniform_u32((uint32_t)sp.lg_src[it]);
+            if (s >= 0) r = uniform_f64(sp.lg_old[s]);
+        }
+    }
+    sum = r;
+    return r * (1.0 / BLK);
+}
+
+// Leave the line's final carry, summed over the lanes in a fixed order, for
+// the next shear along the axis, and its change (final minus starting) for
+// the mass ledger.
+template <int ST>
+__device__ __forceinline__ void leave_residual(const Dev &D, const SweepParams &sp, int64_t it, int lane,
+                                               double carry, double start_sum)
+{
+    if constexpr (ST != VL_F64) {
+        const double s = wave_sum64(carry);
+        if (lane == 0) {
+            if (it < sp.lg_cap) sp.lg_new[it] = s;
+            D.resid[it] = s - start_sum;
+        }
+    }
 }
 
 // max(0, min(x, y)); in FP32 one median-of-three instruction (x >= 0 here,
@@ -443,9 +495,10 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
                 m[w] = (w < WL) ? __builtin_amdgcn_readfirstlane(D.masks[it * D.wlmax + w]) : 0u;
                 pre[w + 1] = pre[w] + __popc(m[w]);
             }
-            if (pre[MAXWL] == 0) {  // empty item: no line, no residual
-                if constexpr (ST != VL_F64)
-                    if (lane == 0) D.resid[it] = 0.0;
+            if (pre[MAXWL] == 0) {  // empty item: no updated cell, the residual passes on
+                double sum;
+                const double r = take_residual<ST>(sp, it, sum);
+                leave_residual<ST>(D, sp, it, lane, r, sum);
                 continue;
             }
 #pragma unroll
@@ -477,7 +530,8 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
         const int bd = block_coord(D, d, item.id);
         const double c = courant(D, d, 4 * bd + ld, sp.dt);
         const unsigned long long npos = __ballot(c > 0.0), nneg = __ballot(c < 0.0);
-        double carry = 0.0;
+        double start_sum;
+        double carry = take_residual<ST>(sp, it, start_sum);
         uint8_t *sflag = s_flag[wv];
         // March each segment of cells holding the block: from its first such
         // cell to three past its last (where the last one is written).  Before
@@ -510,12 +564,8 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
             store_flag_words(D, it, srow, sflag, L, lane);
         }
 
-        if constexpr (ST != VL_F64) {
-            // terminal residual of the item's pencil line (the ledger takes
-            // those of the local pencils)
-            const double r = wave_sum64(carry);
-            if (lane == 0) D.resid[it] = r;
-        }
+        // the line's final carry (the ledger takes those of the local pencils)
+        leave_residual<ST>(D, sp, it, lane, carry, start_sum);
         wave_sync_lds();
     }
 }
@@ -688,7 +738,8 @@ __device__ __forceinline__ void sweep_stream(const Dev &D, const SweepParams &sp
         const int bd = block_coord(D, d, id);
         const double c = courant(D, d, 4 * bd + ld, sp.dt);
         const unsigned long long npos = __ballot(c > 0.0), nneg = __ballot(c < 0.0);
-        double carry = 0.0;
+        double start_sum;
+        double carry = take_residual<ST>(sp, it, start_sum);
         auto build = [&]() {
             build_slots(D, nit, nitems, L, WL, lane, Y);
             wave_sync_lds();
@@ -703,10 +754,7 @@ __device__ __forceinline__ void sweep_stream(const Dev &D, const SweepParams &sp
             wave_sync_lds();
             store_flag_words(D, it, X, sflag, L, lane);
         }
-        if constexpr (ST != VL_F64) {
-            const double r = wave_sum64(carry);  // terminal residual of the line
-            if (lane == 0) D.resid[it] = r;
-        }
+        leave_residual<ST>(D, sp, it, lane, carry, start_sum);  // the line's final carry
         wave_sync_lds();
         uint32_t *tmp = X;
         X = Y;
@@ -785,9 +833,13 @@ static void launch_st(const Dev &D, const SweepParams &sp, int v, hipStream_t st
 int sweep_variants() { return NVARIANTS; }
 
 void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, bool last,
-                  hipStream_t st)
+                  const LedgerIO &lg, hipStream_t st)
 {
     SweepParams sp;
+    sp.lg_old = lg.old.res;
+    sp.lg_new = lg.nw.res;
+    sp.lg_src = lg.src;
+    sp.lg_cap = lg.src ? lg.cap : 0;
     sp.d = d;
     sp.sidx = sidx;
     sp.L = D.P[d];

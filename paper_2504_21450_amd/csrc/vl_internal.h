@@ -160,6 +160,28 @@ __device__ inline int block_dirs(const Dev &D, int d, int32_t b, double dt)
     return r;
 }
 
+// Per-line mass ledger of the reduced storage types.  A store holds, for one
+// shear axis, the work items of its last shear: per item the block id and
+// the FP64 carry left at the end of the pencil line, summed over the block's
+// 64 velocity cells; per pencil (keyed by its padded transverse coordinates
+// t1 + P[e1] t2) the first item and the item count.  The next shear along
+// the same axis starts the carry of each velocity cell of the same (line,
+// block) from 1/64 of that sum (exact in FP64), so rounding residuals go back
+// into f instead of piling up.
+struct LedgerStore {
+    int32_t *ids;     // block id per item
+    double *res;      // residual per item
+    int32_t *kfirst;  // per pencil key: first item
+    int32_t *kcnt;    //   and item count (0: none)
+};
+// the stores one shear reads (old) and writes (nw), and its item -> old item
+// map; all null (cap 0) in FP64 storage, which has no rounding carry
+struct LedgerIO {
+    LedgerStore old, nw;
+    int32_t *src;     // per item of the shear: item of the old store with the same line and block, or -1
+    int64_t cap;      // items a store holds
+};
+
 // ---- launches (defined in the kernel sources, called by the host API) ----
 void launch_book(const Dev &D, int op, hipStream_t st);
 void launch_iota_ring(const Dev &D, int64_t first_free, int64_t count, hipStream_t st);
@@ -180,10 +202,12 @@ void launch_fill_from(const Dev &D, const SrcTable &src, hipStream_t st);
 void launch_fill_box(const Dev &D, const SrcTable &src, const int lo[3], const int hi[3], hipStream_t st);
 SrcPart self_source(const Dev &D);
 void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, int cur,
-                 hipStream_t st);
+                 const LedgerIO &lg, hipStream_t st);
 int sweep_variants();
 void launch_sweep(const Dev &D, int d, int sidx, const int lo[3], const int hi[3], double dt, bool last,
-                  hipStream_t st);
+                  const LedgerIO &lg, hipStream_t st);
+// n int32 zeros at p (a kernel, so that graph captures hold no memset node)
+void launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 // FP64 sum of the terminal residuals of the shear's local pencils into *out:
 // per pencil over its items in id order, then over the pencils in order
 void launch_ledger_sum(const Dev &D, int d, const int lo[3], const int hi[3], double *out, hipStream_t st);
