@@ -63,7 +63,9 @@ enum {
     VL_ERR_STALE_GHOSTS = -4, /* coalesced step without a ghost update */
     VL_ERR_HIP = -5,          /* a HIP runtime call failed */
     VL_ERR_STATE = -6,        /* partition invalid after an earlier error */
-    VL_ERR_SCRATCH = -7       /* vl_moments_static: the fixed scratch array is too small */
+    VL_ERR_SCRATCH = -7,      /* vl_moments_static: the fixed scratch array is too small */
+    VL_ERR_SPLIT = -8         /* vl_accelerate: a cell's velocity map cannot be split
+                                 into three one-coordinate remaps */
 };
 
 /* Partition descriptor (all fields are read by vl_workspace_bytes and
@@ -193,6 +195,37 @@ int vl_fill_ghosts_from(vl_partition *p, vl_partition *const *nbr);
  * Errors: VL_ERR_ARG, VL_ERR_CFL (checked on the host before launch),
  * VL_ERR_STALE_GHOSTS, VL_ERR_CAPACITY (with stats), VL_ERR_STATE, VL_ERR_HIP. */
 int vl_translate_step(vl_partition *p, double dt, int32_t mode, vl_step_stats *stats);
+
+/* Acceleration step: the Lorentz-force term of the Vlasov equation (Section 2,
+ * eq. 1, the velocity-space half of the split step, whose solver Section 2
+ * names as SLICE-3D).  Per local cell, in the cell's fields E, B, constant
+ * over the step, every velocity moves along its exact characteristic: the
+ * affine map v' = A v + c with A the rotation by -qm |B| dt about B/|B| and c
+ * the E x B drift's part plus the acceleration qm (E.b) dt b along b (with
+ * B = 0: v' = v + qm E dt).  The map is applied as three one-coordinate maps
+ * in slice_order (a permutation of {0,1,2}, NULL = x, y, z), each setting one
+ * velocity coordinate to its final value: a conservative remap of every
+ * velocity column along that axis, cell i receiving the mass of its pre-image
+ * under the CW84 parabolas of the column (the spatial remap's slopes, faces
+ * and limiter).  Mass moved beyond the velocity mesh is lost.  The cell's
+ * block set becomes its old blocks plus every block holding a nonzero value,
+ * then the end-of-step pruning (sparse_min, vbuffer) as after a translation
+ * step.  Computed in FP64 from any storage; the result is rounded to the
+ * storage type (no rounding carry).
+ *   dev_fields: device, 6 doubles per local cell (Ex, Ey, Ez [V/m],
+ *               Bx, By, Bz [T]), x fastest, read only during the call.
+ *   qm: charge-to-mass ratio [C/kg]; dt > 0 [s].
+ *   stats: optional host output (mass before and after, pruned mass, local
+ *          blocks; no ledger); if non-NULL the call synchronises again.
+ * The call synchronises once to check the maps: if some cell's map cannot be
+ * split (a step's own coefficient not positive, e.g. a rotation of half a
+ * turn or more) it returns VL_ERR_SPLIT with f unchanged.  Velocity meshes of
+ * more than 64 blocks along an axis are not supported (VL_ERR_ARG).  The
+ * ghost domain is stale afterwards.
+ * Errors: VL_ERR_ARG, VL_ERR_SPLIT, VL_ERR_CAPACITY (with stats), VL_ERR_STATE,
+ * VL_ERR_HIP. */
+int vl_accelerate(vl_partition *p, double dt, double qm, const double *dev_fields, const int32_t *slice_order,
+                  vl_step_stats *stats);
 
 /* nsteps whole steps, each recorded once into a HIP graph and replayed: in
  * VL_COALESCED mode the coalesced ghost update followed by the three shears

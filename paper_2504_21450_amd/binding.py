@@ -19,13 +19,14 @@ VL_COALESCED, VL_PER_SWEEP = 0, 1
 VL_OK, VL_ERR_ARG, VL_ERR_CFL, VL_ERR_CAPACITY, VL_ERR_STALE_GHOSTS, VL_ERR_HIP, VL_ERR_STATE = (
     0, -1, -2, -3, -4, -5, -6)
 VL_ERR_SCRATCH = -7
+VL_ERR_SPLIT = -8
 
 EXPORTED = ("vl_workspace_bytes", "vl_init_partition", "vl_load_values", "vl_fill_ghosts", "vl_fill_ghosts_from", "vl_translate_step",
             "vl_moments", "vl_local_block_count", "vl_export_state", "vl_export_cells",
             "vl_set_courant_override", "vl_counters", "vl_profile_start", "vl_profile_stop",
             "vl_autotune", "vl_set_variant", "vl_set_shear_variants", "vl_get_shear_variants",
             "vl_graph_step", "vl_sync", "vl_destroy",
-            "vl_status_string", "vl_moments_static")
+            "vl_status_string", "vl_moments_static", "vl_accelerate")
 
 
 class VlDesc(C.Structure):
@@ -79,6 +80,8 @@ def load():
     L.vl_moments.argtypes = [vp, vp, vp, vp, vp]
     L.vl_moments_static.restype = C.c_int
     L.vl_moments_static.argtypes = [vp, vp, vp, vp, vp]
+    L.vl_accelerate.restype = C.c_int
+    L.vl_accelerate.argtypes = [vp, dbl, dbl, vp, vp, C.POINTER(VlStepStats)]
     L.vl_local_block_count.restype = C.c_int
     L.vl_local_block_count.argtypes = [vp, C.POINTER(i64)]
     L.vl_export_state.restype = C.c_int
@@ -231,6 +234,29 @@ class Partition:
                 "pruned_mass": st.pruned_mass, "ledger_mass": st.ledger_mass,
                 "blocks": st.local_blocks, "updated_ps": tuple(st.updated_ps),
                 "read_ps": tuple(st.read_ps), "items": tuple(st.items)}
+
+    def accelerate(self, dt, qm, fields, order=None, stats=False):
+        """Acceleration step in per-cell fields: `fields` is a device FP64
+        tensor of 6 values per local cell (Ex, Ey, Ez, Bx, By, Bz), x fastest;
+        order: the slice order (default x, y, z)."""
+        t = self.torch
+        assert fields.device.type == "cuda" and fields.dtype == t.float64 and fields.is_contiguous()
+        assert fields.numel() == 6 * self.ncell
+        o = (C.c_int32 * 3)(*order) if order is not None else None
+        st = VlStepStats() if stats else None
+        rc = self.lib.vl_accelerate(self.h, float(dt), float(qm), C.c_void_p(fields.data_ptr()), o,
+                                    C.byref(st) if stats else None)
+        if rc != VL_OK and stats and st.device_errors:
+            raise VlasovError("vl_accelerate (device error bits %#x)" % st.device_errors, rc)
+        _check("vl_accelerate", rc)
+        if not stats:
+            return None
+        return {"mass_before": st.mass_before, "mass_after": st.mass_after,
+                "pruned_mass": st.pruned_mass, "blocks": st.local_blocks}
+
+    def accelerate_rc(self, dt, qm, fields, order=None):
+        o = (C.c_int32 * 3)(*order) if order is not None else None
+        return self.lib.vl_accelerate(self.h, float(dt), float(qm), C.c_void_p(fields.data_ptr()), o, None)
 
     def fill_ghosts_from(self, nbr):
         """Ghost update from the 27 partitions around this one (nbr[13] is

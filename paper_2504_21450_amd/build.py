@@ -24,7 +24,7 @@ GEN_LIB = os.path.join(HERE, "libvlgen.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "k_store.hip", "k_plan.hip", "k_sweep.hip", "k_prune.hip"]
+SOURCES = ["api.hip", "k_store.hip", "k_plan.hip", "k_sweep.hip", "k_prune.hip", "k_accel.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

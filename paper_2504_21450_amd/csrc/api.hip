@@ -24,7 +24,7 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
     size_t pool, ring, lstart, lcount, lcapa, lsorted, lid, lslot, litem, rows, items, masks, resid, penfirst,
         pencnt, pensum, ctl, cover, cellred, red, cellcnt, mom, lg_ids[4], lg_res[4], lg_kfirst[4],
-        lg_kcnt[4], lg_src, total;
+        lg_kcnt[4], lg_src, accel, total;
     int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap, pen_cap, mom_parts, lg_cap;
     int tab_stride;
     int wlmax, cover_stride;
@@ -119,6 +119,8 @@ Layout make_layout(const vl_desc *d)
         L.lg_kcnt[k] = o;   o = align_up(o + (size_t)(L.lg_cap ? L.pen_cap : 0) * 4);
     }
     L.lg_src = o;  o = align_up(o + (size_t)L.lg_cap * 4);
+    // acceleration: the velocity maps of the local cells
+    L.accel = o;   o = align_up(o + (size_t)L.nlocal * ACC_MAP_DOUBLES * 8);
     L.total = o;
     return L;
 }
@@ -402,6 +404,7 @@ const char *vl_status_string(int s)
     case VL_ERR_HIP: return "HIP runtime error";
     case VL_ERR_STATE: return "partition invalid after an earlier error";
     case VL_ERR_SCRATCH: return "the partition needs more scratch than the fixed device array of vl_moments_static holds";
+    case VL_ERR_SPLIT: return "a cell's velocity map cannot be split into three one-coordinate remaps (rotation too large for the step)";
     default: return "unknown status";
     }
 }
@@ -760,6 +763,91 @@ int vl_graph_step(vl_partition *p, double dt, int32_t mode, int32_t nsteps)
         p->cur = 1 - p->cur;
         rotate(p->rot, p->desc.order, p->lay.lg_cap > 0);
         p->ghosts_valid = false;
+    }
+    return VL_OK;
+}
+
+int vl_accelerate(vl_partition *p, double dt, double qm, const double *dev_fields, const int32_t *slice_order,
+                  vl_step_stats *stats)
+{
+    if (!p) return VL_ERR_ARG;
+    if (p->bad) return VL_ERR_STATE;
+    if (!(dt > 0.0) || !isfinite(dt) || !isfinite(qm) || !dev_fields) return VL_ERR_ARG;
+    int order[3] = {0, 1, 2};
+    if (slice_order) {
+        int seen = 0;
+        for (int k = 0; k < 3; k++) {
+            if (slice_order[k] < 0 || slice_order[k] > 2) return VL_ERR_ARG;
+            order[k] = slice_order[k];
+            seen |= 1 << order[k];
+        }
+        if (seen != 7) return VL_ERR_ARG;
+    }
+    const Dev &D = p->D;
+    hipStream_t st = p->stream;
+    {
+        int ncols = 0, hc = 0, dev = 0, maxlds = 0;
+        const size_t lds = accel_lds_bytes(D, &ncols, &hc);
+        VL_HIP(hipGetDevice(&dev));
+        VL_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        if (lds == 0 || lds + 2048 > (size_t)maxlds) return VL_ERR_ARG;  // + the kernel's static LDS
+    }
+    double *maps = (double *)(p->ws + p->lay.accel);
+    int *bad = (int *)(D.red + 64);
+    // the maps first: a cell whose map cannot be split leaves f untouched
+    launch_zero_i32(bad, 1, st);
+    launch_accel_maps(D, dev_fields, maps, bad, qm, dt, order, st);
+    VL_HIP(hipGetLastError());
+    int hbad = 0;
+    VL_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    VL_HIP(hipStreamSynchronize(st));
+    if (hbad) return VL_ERR_SPLIT;
+    if (stats) {
+        launch_cell_mass(D, st);
+        launch_reduce(D, D.cell_red, D.nlocal, D.red + 0, st);
+    }
+    const int nxt = 1 - p->cur;
+    p->loadable = false;
+    launch_book(D, BOOK_STEP_RESET, st);
+    launch_book(D, BOOK_SWEEP_RESET, st);  // ring limit <- tail
+    {
+        ProfScope ps(p, K_OTHER);
+        if (launch_accel(D, maps, order, p->cur, st)) return VL_ERR_ARG;
+    }
+    launch_book(D, nxt == 0 ? BOOK_PRUNE_RESET_A : BOOK_PRUNE_RESET_B, st);
+    {
+        ProfScope ps(p, K_PRUNE);
+        launch_prune(D, nxt, -1, st);
+    }
+    VL_HIP(hipGetLastError());
+    p->cur = nxt;
+    p->ghosts_valid = false;
+    if (stats) {
+        launch_reduce(D, D.cell_red, D.nlocal, D.red + 2, st);  // pruned mass
+        launch_cell_mass(D, st);
+        launch_reduce(D, D.cell_red, D.nlocal, D.red + 1, st);
+        launch_cell_counts(D, st);
+        VL_HIP(hipGetLastError());
+        double red[3];
+        Ctl ctl;
+        std::vector<int32_t> cc((size_t)D.nlocal);
+        VL_HIP(hipMemcpyAsync(red, D.red, sizeof(red), hipMemcpyDeviceToHost, st));
+        VL_HIP(hipMemcpyAsync(&ctl, D.ctl, sizeof(ctl), hipMemcpyDeviceToHost, st));
+        VL_HIP(hipMemcpyAsync(cc.data(), D.cell_cnt, cc.size() * 4, hipMemcpyDeviceToHost, st));
+        VL_HIP(hipStreamSynchronize(st));
+        const double vol = D.dx[0] * D.dx[1] * D.dx[2] * D.dv[0] * D.dv[1] * D.dv[2];
+        memset(stats, 0, sizeof(*stats));
+        stats->mass_before = red[0] * vol;
+        stats->mass_after = red[1] * vol;
+        stats->pruned_mass = red[2];
+        int64_t nb = 0;
+        for (int32_t v : cc) nb += v;
+        stats->local_blocks = nb;
+        stats->device_errors = (uint64_t)ctl.err;
+        if (ctl.err) {
+            p->bad = true;
+            return VL_ERR_CAPACITY;
+        }
     }
     return VL_OK;
 }

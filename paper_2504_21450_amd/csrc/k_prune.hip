@@ -3,10 +3,13 @@
 // local cell:
 //   content = blocks with a value >= sparse_min: bit t (the cell's place along
 //             the last shear's pencil) of the content-flag words that the last
-//             shear left in its work item of the block (list entry -> item),
+//             shear left in its work item of the block (list entry -> item);
+//             after an acceleration step, bit 0 of the flags it left per list
+//             entry,
 //   keep    = content dilated by the velocity-space buffer (0, 6 or 26
-//             neighbours, clipped to the mesh); keep = all blocks if pruning is
-//             off,
+//             neighbours, clipped to the mesh); if pruning is off, all blocks
+//             (after an acceleration step: all but the blocks it created that
+//             hold only zeros),
 //   removed blocks: their mass goes to the pruned-mass ledger and their slots
 //             back to the free ring; created blocks get zeroed slots,
 //   the list is rewritten sorted by block id into the other local list
@@ -56,6 +59,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
     const bool prune = D.sparse_min > 0.0;
     const int nbx = D.nblk[0], nby = D.nblk[1], nbz = D.nblk[2];
     // the cell's word and bit in the last shear's content flags
+    const bool accel = last_axis < 0;
     const int tc = H + (last_axis == 0 ? x : last_axis == 1 ? y : z);
     const uint32_t *fw = D.masks + (tc >> 5);
     const uint32_t fbit = 1u << (tc & 31);
@@ -74,13 +78,22 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
         const int32_t id = D.lid[cs + e];
         const int32_t slot = D.lslot[cs + e];
         atomicOr(&s_old[id >> 5], 1u << (id & 31));
-        if (!prune) {
-            atomicOr(&s_keep[id >> 5], 1u << (id & 31));
-            continue;
+        if (accel) {
+            const int fl = D.litem[cs + e];
+            if (!prune) {
+                if (!(fl & 4) || (fl & 2)) atomicOr(&s_keep[id >> 5], 1u << (id & 31));
+                continue;
+            }
+            if (!(fl & 1)) continue;
+        } else {
+            if (!prune) {
+                atomicOr(&s_keep[id >> 5], 1u << (id & 31));
+                continue;
+            }
+            if ((int64_t)slot >= D.lcap) continue;  // scratch slot of a failed allocation
+            const uint32_t it = (uint32_t)D.litem[cs + e];
+            if ((uint64_t)it >= nitems || !(fw[(int64_t)it * D.wlmax] & fbit)) continue;
         }
-        if ((int64_t)slot >= D.lcap) continue;  // scratch slot of a failed allocation
-        const uint32_t it = (uint32_t)D.litem[cs + e];
-        if ((uint64_t)it >= nitems || !(fw[(int64_t)it * D.wlmax] & fbit)) continue;
         const int bx = id % nbx, by = (id / nbx) % nby, bz = id / (nbx * nby);
         for (int oz = -1; oz <= 1; oz++)
             for (int oy = -1; oy <= 1; oy++)

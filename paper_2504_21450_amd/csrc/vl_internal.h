@@ -211,7 +211,20 @@ void launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 // FP64 sum of the terminal residuals of the shear's local pencils into *out:
 // per pencil over its items in id order, then over the pencils in order
 void launch_ledger_sum(const Dev &D, int d, const int lo[3], const int hi[3], double *out, hipStream_t st);
+// last_axis < 0: the acceleration step's flags per list entry (bit 0 content,
+// bit 1 nonzero, bit 2 created in the step) instead of a shear's content flags
 void launch_prune(const Dev &D, int nxt_region, int last_axis, hipStream_t st);
+// acceleration step: per local cell the three one-coordinate maps of the
+// velocity map in the given order (ACC_MAP doubles each; *bad set to nonzero
+// if a cell's map cannot be split), then the three remaps of every cell's
+// velocity space; launch_accel returns -1 if the velocity mesh is beyond the
+// kernel's limits (more than ACC_MAX_NBLK blocks along an axis)
+constexpr int ACC_MAX_NBLK = 64;
+constexpr int ACC_MAP_DOUBLES = 12;
+void launch_accel_maps(const Dev &D, const double *fields, double *maps, int *bad, double qm, double dt,
+                       const int order[3], hipStream_t st);
+size_t accel_lds_bytes(const Dev &D, int *ncols, int *hc);
+int launch_accel(const Dev &D, double *maps, const int order[3], int cur, hipStream_t st);
 void launch_cell_mass(const Dev &D, hipStream_t st);
 void launch_reduce(const Dev &D, const double *in, int64_t n, double *out, hipStream_t st);
 // scratch of the moments: per local cell the first partial slot of a split

@@ -95,7 +95,7 @@ def test_init_rejects_bad_arguments_without_a_gpu():
 
 
 def test_status_strings():
-    for s in (0, -1, -2, -3, -4, -5, -6, -7):
+    for s in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert len(B.status_string(s)) >= 2
     assert "Courant" in B.status_string(B.VL_ERR_CFL)
 
