@@ -288,6 +288,54 @@ def run(p, w, storage, mode, steps, warmup, tune_steps, variant=None, graph_step
     return out
 
 
+def accel_run(kind, n, hot, storage, steps, slack=3.0):
+    """Acceleration steps (the Lorentz-force half of the split step) on a
+    partition of their own, in seeded per-cell fields: time per step, and the
+    remap kernel's algorithmic bytes (each of the three remaps reads and
+    writes every block once: 6 x 64 values per block) per launch over its
+    HIP-event time.  The blocks that the three remaps create stay until the
+    step's pruning, so the pool needs room for about half as many again as
+    the hot cells hold (slack 3)."""
+    import torch
+
+    from paper_2504_21450_amd import workloads as W
+
+    t0 = time.time()
+    w, p = make_partition(kind, n, hot, storage, slack, (0, 1, 2), 3)
+    log("acceleration workload %s %s: %d blocks, workspace %.1f GB (%.0f s)" % (
+        "x".join(map(str, n)), storage, w.nblocks, p.ws_bytes / 1e9, time.time() - t0))
+    EB, dt = W.lorentz_fields(p.ncell)
+    fields = torch.tensor(EB.reshape(-1), dtype=torch.float64, device="cuda:0")
+    qm = 9.58e7
+    p.accelerate(dt, qm, fields)  # warm-up
+    p.sync()
+    b0 = p.local_blocks()
+    p.profile_start(16 * steps + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.accelerate(dt, qm, fields)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = p.profile_stop()
+    b1 = p.local_blocks()
+    ms, nl = prof["accel"]
+    bytes_per_launch = 6 * 64 * BYTES[storage] * 0.5 * (b0 + b1)
+    gbs = bytes_per_launch / (ms / max(nl, 1) / 1e3) / 1e9 if nl else None
+    del fields
+    p.close()
+    del p
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "storage": storage, "initial_blocks": int(w.nblocks),
+            "fields": "seeded per-cell E, B (|B| 5-15 nT, random direction; E x B drift ~1e5 m/s; "
+                      "parallel E up to 2 velocity cells per step); gyration 0.15-0.45 rad per step",
+            "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "kernel_ms_per_step": {"accel": ms / steps, "prune": prof["prune"][0] / steps},
+            "local_blocks": int(b1), "algorithmic_bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": ms / max(nl, 1), "gbs": gbs, "frac_of_hbm_peak": (gbs or 0.0) / HBM_PEAK_GBS,
+            "block_updates_per_s": 3 * 0.5 * (b0 + b1) * 64 * steps / el}
+
+
 def side_run(kind, n, hot, storage, steps, tune_steps, slack=1.8):
     """A shorter measurement of another workload or storage (for the extras)."""
     import torch
@@ -338,6 +386,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=None,
                     help="steps replayed from recorded HIP graphs after the timed region "
                          "(default: min(--steps, 10); 0 to skip)")
+    ap.add_argument("--accel-steps", type=int, default=3,
+                    help="acceleration steps timed after the translation steps (0 to skip)")
     ap.add_argument("--extra-steps", type=int, default=5,
                     help="timed steps of the FP32 reference and of the FP32-vs-FP64 comparison "
                          "(0 skips both)")
@@ -433,6 +483,12 @@ def main():
     }
     if "graph" in r:
         out["graph"] = r["graph"]
+    if args.accel_steps > 0:
+        acc_n = (n[0], n[1], max(1, n[2] // 2)) if mixture else n
+        acc = accel_run(args.workload, acc_n, args.hot, storage, args.accel_steps)
+        log("acceleration: %.2f ms/step, remap kernel %.2f ms (%.0f GB/s)" % (
+            acc["ms_per_step"], acc["avg_launch_ms"], acc["gbs"] or 0.0))
+        out["acceleration"] = acc
     if mixture and args.extra_steps > 0:
         ref_n = (n[0], n[1], max(1, n[2] // 2))
         log("FP32 reference at %s ..." % "x".join(map(str, ref_n)))

@@ -298,12 +298,13 @@ int vl_set_courant_override(vl_partition *p, const double *table, int32_t stride
 int vl_counters(vl_partition *p, uint64_t *out, int32_t n);
 
 /* Diagnostics: kernel timing with HIP events recorded on the partition's
- * stream around every launch of the ghost update, planner, shear, pruning and
- * moment kernels, for up to max_launches launches after vl_profile_start.
+ * stream around every launch of the ghost update, planner, shear, pruning,
+ * moment and acceleration kernels, for up to max_launches launches after
+ * vl_profile_start.
  * vl_profile_stop synchronises and returns, per class (0 ghost update,
  * 1 planner, 2 shears (all), 3 pruning, 4 moments, 5/6/7 first/second/third
- * shear of the step), the summed milliseconds ms[8] and the launch counts
- * launches[8], then stops recording. */
+ * shear of the step, 8 acceleration remaps), the summed milliseconds ms[9]
+ * and the launch counts launches[9], then stops recording. */
 int vl_profile_start(vl_partition *p, int32_t max_launches);
 int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches);
 

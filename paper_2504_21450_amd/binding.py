@@ -313,14 +313,15 @@ class Partition:
         _check("vl_counters", self.lib.vl_counters(self.h, _ptr(out), 23))
         return {k: int(v) for k, v in zip(self.COUNTER_NAMES, out)}
 
-    KERNEL_CLASSES = ("ghost_fill", "planner", "shear", "prune", "moments", "shear1", "shear2", "shear3")
+    KERNEL_CLASSES = ("ghost_fill", "planner", "shear", "prune", "moments", "shear1", "shear2", "shear3",
+                      "accel")
 
     def profile_start(self, max_launches=4096):
         _check("vl_profile_start", self.lib.vl_profile_start(self.h, int(max_launches)))
 
     def profile_stop(self):
-        ms = np.zeros(8)
-        n = np.zeros(8, np.int64)
+        ms = np.zeros(len(self.KERNEL_CLASSES))
+        n = np.zeros(len(self.KERNEL_CLASSES), np.int64)
         _check("vl_profile_stop", self.lib.vl_profile_stop(self.h, _ptr(ms), _ptr(n)))
         return {k: (float(a), int(c)) for k, a, c in zip(self.KERNEL_CLASSES, ms, n)}
 

@@ -193,7 +193,7 @@ int hip_ok(hipError_t e) { return e == hipSuccess ? VL_OK : VL_ERR_HIP; }
     } while (0)
 
 // kernel classes timed by the profiler
-enum { K_FILL = 0, K_PLAN = 1, K_SWEEP = 2, K_PRUNE = 3, K_OTHER = 4, K_SHEAR0 = 5, K_NCLS = 8 };
+enum { K_FILL = 0, K_PLAN = 1, K_SWEEP = 2, K_PRUNE = 3, K_OTHER = 4, K_SHEAR0 = 5, K_ACCEL = 8, K_NCLS = 9 };
 
 struct ProfScope {
     vl_partition *p;
@@ -811,7 +811,7 @@ int vl_accelerate(vl_partition *p, double dt, double qm, const double *dev_field
     launch_book(D, BOOK_STEP_RESET, st);
     launch_book(D, BOOK_SWEEP_RESET, st);  // ring limit <- tail
     {
-        ProfScope ps(p, K_OTHER);
+        ProfScope ps(p, K_ACCEL);
         if (launch_accel(D, maps, order, p->cur, st)) return VL_ERR_ARG;
     }
     launch_book(D, nxt == 0 ? BOOK_PRUNE_RESET_A : BOOK_PRUNE_RESET_B, st);

@@ -26,9 +26,12 @@
 //   * blocks of that span missing from the cell are created: slots from the
 //     free ring, entries merged into the sorted list (in place from the end,
 //     or into a larger place when the list outgrows it);
-//   * each wavefront stages a block column in LDS (16 velocity columns x its
-//     span, missing blocks as zero) and writes every block of the span, 64
-//     lanes = the block's 64 cells, so loads and stores are coalesced;
+//   * the workgroup remaps one block column at a time: it stages the column
+//     in LDS (16 velocity columns x its span, missing blocks as zero; eight
+//     blocks' loads in flight per wavefront), the limited parabola edges of
+//     every cell once, then the new averages, writing every block of the
+//     span, 64 lanes = the block's 64 cells, so loads and stores are
+//     coalesced;
 //   * the last remap leaves per list entry the flags the pruning reads:
 //     bit 0 a value >= the content threshold, bit 1 a nonzero value, bit 2
 //     created by this step.
@@ -132,53 +135,50 @@ __global__ __launch_bounds__(256) void k_accel_factors(Dev D, AccelParams ap)
 // ---------------------------------------------------------------------------
 // column remap
 // ---------------------------------------------------------------------------
-// limited slope of cell j of a column (CW84 eq. 1.7-1.8); a(.) reads zero
-// outside the staged span
-template <typename A>
-__device__ __forceinline__ double col_slope(const A &a, int j)
+// limited slope of cell j of a column (CW84 eq. 1.7-1.8) from its average
+// a0 and its neighbours' am, ap: the central difference, limited to twice
+// either one-sided difference, zero at an extremum
+__device__ __forceinline__ double col_slope(double am, double a0, double ap)
 {
-    const double am = a(j - 1), a0 = a(j), ap = a(j + 1);
     const double dl = a0 - am, dr = ap - a0;
-    if (!(dr * dl > 0.0)) return 0.0;
     const double central = 0.5 * (ap - am);
-    double m = fabs(central);
-    if (2.0 * fabs(dl) < m) m = 2.0 * fabs(dl);
-    if (2.0 * fabs(dr) < m) m = 2.0 * fabs(dr);
-    return central > 0.0 ? m : -m;
+    const double m = fmin(fabs(central), fmin(2.0 * fabs(dl), 2.0 * fabs(dr)));
+    return (dr * dl > 0.0) ? copysign(m, central) : 0.0;
 }
 
-// mass of source cell j's limited parabola (CW84 eq. 1.6, 1.10) over [xa, xb]
-// of the cell (0 <= xa < xb <= 1, in cell units)
-template <typename A>
-__device__ __forceinline__ double col_integral(const A &a, int j, double xa, double xb)
+// limited parabola edges (l, r) of a cell from the averages of cells
+// j-2 .. j+2 (CW84 eq. 1.6 faces from the limited slopes, then the eq. 1.10
+// limiter)
+__device__ __forceinline__ void col_edges(double amm, double am, double a0, double ap, double app, double &l,
+                                          double &r)
 {
-    const double am = a(j - 1), a0 = a(j), ap = a(j + 1);
-    const double dm = col_slope(a, j - 1), d0 = col_slope(a, j), dp = col_slope(a, j + 1);
-    double l = am + 0.5 * (a0 - am) - (d0 - dm) / 6.0;
-    double r = a0 + 0.5 * (ap - a0) - (dp - d0) / 6.0;
+    constexpr double SIXTH = 1.0 / 6.0;
+    const double dm = col_slope(amm, am, a0), d0 = col_slope(am, a0, ap), dp = col_slope(a0, ap, app);
+    l = am + 0.5 * (a0 - am) - (d0 - dm) * SIXTH;
+    r = a0 + 0.5 * (ap - a0) - (dp - d0) * SIXTH;
     if ((r - a0) * (a0 - l) <= 0.0) {
         l = a0;
         r = a0;
     } else {
         const double dd = r - l;
         const double mm = a0 - 0.5 * (l + r);
-        if (dd * mm > dd * dd / 6.0)
+        if (dd * mm > dd * dd * SIXTH)
             l = 3.0 * a0 - 2.0 * r;
-        else if (-(dd * dd) / 6.0 > dd * mm)
+        else if (-(dd * dd) * SIXTH > dd * mm)
             r = 3.0 * a0 - 2.0 * l;
     }
-    const double a6 = 6.0 * (a0 - 0.5 * (l + r));
-    const double dA = r - l;
-    return l * (xb - xa) + 0.5 * (dA + a6) * (xb * xb - xa * xa) - a6 * (xb * xb * xb - xa * xa * xa) / 3.0;
 }
 
-// new average of cell i of a column of N cells moved by u -> alpha u + sigma:
-// the mass of [(i - sigma)/alpha, (i + 1 - sigma)/alpha] under the source
-// parabolas; a source cell covered whole gives its average
-template <typename A>
-__device__ __forceinline__ double col_remap_cell(const A &a, int N, int i, double alpha, double sigma)
+// new average of cell i of a column of N cells moved by u -> alpha u + sigma
+// (inv_alpha = 1 / alpha): the mass of [(i - sigma)/alpha, (i + 1 - sigma)/alpha]
+// under the source parabolas (average a, edges l, r); a source cell covered
+// whole gives its average
+template <typename A, typename E>
+__device__ __forceinline__ double col_remap_cell(const A &a, const E &edges, int N, int i, double inv_alpha,
+                                                 double sigma)
 {
-    const double lo = ((double)i - sigma) / alpha, hi = ((double)i + 1.0 - sigma) / alpha;
+    constexpr double THIRD = 1.0 / 3.0;
+    const double lo = ((double)i - sigma) * inv_alpha, hi = ((double)i + 1.0 - sigma) * inv_alpha;
     // source cells floor(lo) .. floor(hi) within the mesh (bounded before the
     // conversion, so a pre-image far off the mesh gives an empty range)
     const double fl = floor(lo), fh = floor(hi);
@@ -190,11 +190,16 @@ __device__ __forceinline__ double col_remap_cell(const A &a, int N, int i, doubl
         if (xa < 0.0) xa = 0.0;
         if (xb > 1.0) xb = 1.0;
         if (!(xb > xa)) continue;
+        const double a0 = a(j);
         if (xa == 0.0 && xb == 1.0) {
-            m += a(j);
+            m += a0;
             continue;
         }
-        m += col_integral(a, j, xa, xb);
+        double l, r;
+        edges(j, l, r);
+        const double a6 = 6.0 * (a0 - 0.5 * (l + r));
+        const double dA = r - l;
+        m += l * (xb - xa) + 0.5 * (dA + a6) * (xb * xb - xa * xa) - a6 * (xb * xb * xb - xa * xa * xa) * THIRD;
     }
     return m;
 }
@@ -271,7 +276,19 @@ __global__ __launch_bounds__(256) void k_accel(Dev D, AccelParams ap)
     int *s_rank = (int *)(s_start + W);    // W + 1
     int *s_span = s_rank + (W + 1);        // per block column: lo | hi << 16, or -1
     int *s_new = s_span + ap.ncols;        // per block column: blocks created (then their prefix)
-    double *s_stage = (double *)(((uintptr_t)(s_new + ap.ncols) + 15) & ~(uintptr_t)15) + (size_t)wv * 16 * ap.hc;
+    // per wavefront: the block column it remaps, 16 velocity columns of
+    // hc + 1 cells (odd stride: fewer bank conflicts), and the slots of the
+    // column's blocks
+    // (byte offsets from the LDS array itself, so the compiler keeps these
+    // pointers in the LDS address space): the block column being remapped,
+    // averages and limited edges of 16 velocity columns of hc + 1 cells (odd
+    // stride: fewer bank conflicts), and per wavefront the slots of its blocks
+    const int hcs = ap.hc + 1;
+    const int stage_off = (4 * (3 * W + (W + 1) + 2 * ap.ncols) + 15) & ~15;
+    double *s_a = (double *)(smem + stage_off);
+    double *s_l = s_a + 16 * hcs;
+    double *s_r = s_l + 16 * hcs;
+    int32_t *s_sl = (int32_t *)(s_r + 16 * hcs) + wv * (ap.hc / 16 + 1);
 
     const int64_t q = blockIdx.x;
     const int x = (int)(q % D.n[0]), y = (int)((q / D.n[0]) % D.n[1]), z = (int)(q / ((int64_t)D.n[0] * D.n[1]));
@@ -434,55 +451,92 @@ __global__ __launch_bounds__(256) void k_accel(Dev D, AccelParams ap)
             __syncthreads();
             acc_scan(s_rank, W, s_tmp);
         }
-        // 4. remap the block columns, a wavefront each
+        // 4. remap the block columns one at a time, the workgroup together:
+        //    wavefront w stages the blocks lo + w, lo + w + 4, .. (slots and
+        //    values of up to eight in flight together), the workgroup computes
+        //    the limited edges of every cell once, then wavefront w writes the
+        //    new averages of its blocks (64 lanes = a block's 64 cells)
         const bool last = k == 2;
+        const double inv_alpha = 1.0 / alpha;
         const int ld = (d == 0) ? lx : (d == 1) ? ly : lz;
         const int l1 = (e1 == 0) ? lx : ly, l2 = (e2 == 1) ? ly : lz;
         const int cc = l1 + 4 * l2;
-        double *stg = s_stage + (size_t)cc * ap.hc;
-        for (int col = wv; col < ncol; col += 4) {
+        for (int col = 0; col < ncol; col++) {
             const int sp = s_span[col];
             if (sp < 0) continue;
             const int lo = sp & 0xffff, hi = sp >> 16;
             const int b1 = col % nb1, b2 = col / nb1;
             const int ncell = 4 * (hi - lo + 1);
-            for (int bd = lo; bd <= hi; bd++) {
-                const int32_t id = compose_id(D, d, e1, e2, bd, b1, b2);
-                double v = 0.0;
-                if (has_bit(s_old, id)) {
-                    const int32_t slot = D.lslot[ns + rank_of(s_bm, s_rank, id)];
-                    v = Storage<ST>::load(D.pool, (int64_t)slot * BLK + lane);
+            const int nmine = (hi - lo >= wv) ? (hi - lo - wv) / 4 + 1 : 0;  // blocks of this wavefront
+            for (int u0 = 0; u0 < nmine; u0 += 8) {
+                int32_t sl[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    sl[u] = -1;
+                    if (u0 + u < nmine) {
+                        const int32_t id = compose_id(D, d, e1, e2, lo + wv + 4 * (u0 + u), b1, b2);
+                        const int32_t slot = D.lslot[ns + rank_of(s_bm, s_rank, id)];
+                        sl[u] = __builtin_amdgcn_readfirstlane(has_bit(s_old, id) ? slot : -1 - slot);
+                    }
                 }
-                stg[4 * (bd - lo) + ld] = v;
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    v[u] = (u0 + u < nmine && sl[u] >= 0) ? Storage<ST>::load(D.pool, (int64_t)sl[u] * BLK + lane)
+                                                          : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (u0 + u < nmine) {
+                        s_a[cc * hcs + 4 * (wv + 4 * (u0 + u)) + ld] = v[u];
+                        if (lane == 0) s_sl[u0 + u] = sl[u];
+                    }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __syncthreads();
             const int base = 4 * lo;
-            auto a = [&](int j) -> double {
-                const int r = j - base;
-                return (r >= 0 && r < ncell) ? stg[r] : 0.0;
-            };
-            const double sigma = col_sigma(D, row, d, e1, e2, 4 * b1 + l1, 4 * b2 + l2);
-            for (int bd = lo; bd <= hi; bd++) {
-                const int32_t id = compose_id(D, d, e1, e2, bd, b1, b2);
-                const int pos = rank_of(s_bm, s_rank, id);
-                const int32_t slot = D.lslot[ns + pos];
-                const double v = col_remap_cell(a, N, 4 * bd + ld, alpha, sigma);
-                Storage<ST>::store(D.pool, (int64_t)slot * BLK + lane, v);
-                if (last) {
-                    const double sv = Storage<ST>::round(v);
-                    const bool content = sv >= D.sparse_min, nz = sv != 0.0;
-                    const unsigned long long bc = __ballot(content), bz = __ballot(nz);
-                    if (lane == 0)
-                        D.litem[ns + pos] = (bc ? 1 : 0) | (bz ? 2 : 0) | (has_bit(s_start, id) ? 0 : 4);
+            for (int t = tid; t < 16 * ncell; t += 256) {
+                const int tc = t & 15, j = t >> 4;
+                const double *ac = s_a + tc * hcs;
+                const double amm = j >= 2 ? ac[j - 2] : 0.0, am = j >= 1 ? ac[j - 1] : 0.0, a0 = ac[j];
+                const double ap = j + 1 < ncell ? ac[j + 1] : 0.0, app = j + 2 < ncell ? ac[j + 2] : 0.0;
+                double l, r;
+                col_edges(amm, am, a0, ap, app, l, r);
+                s_l[tc * hcs + j] = l;
+                s_r[tc * hcs + j] = r;
+            }
+            __syncthreads();
+            {
+                const double *ac = s_a + cc * hcs, *lc = s_l + cc * hcs, *rc = s_r + cc * hcs;
+                // cells outside the span hold zero: flat zero parabolas
+                auto a = [&](int jj) -> double {
+                    const int q = jj - base;
+                    return (q >= 0 && q < ncell) ? ac[q] : 0.0;
+                };
+                auto edges = [&](int jj, double &l, double &r) {
+                    const int q = jj - base;
+                    const bool in = q >= 0 && q < ncell;
+                    l = in ? lc[q] : 0.0;
+                    r = in ? rc[q] : 0.0;
+                };
+                const double sigma = col_sigma(D, row, d, e1, e2, 4 * b1 + l1, 4 * b2 + l2);
+                for (int u = 0; u < nmine; u++) {
+                    const int bd = lo + wv + 4 * u;
+                    const int32_t sl = __builtin_amdgcn_readfirstlane(s_sl[u]);
+                    const int32_t slot = sl >= 0 ? sl : -1 - sl;
+                    const double v = col_remap_cell(a, edges, N, 4 * bd + ld, inv_alpha, sigma);
+                    Storage<ST>::store(D.pool, (int64_t)slot * BLK + lane, v);
+                    if (last) {
+                        const int32_t id = compose_id(D, d, e1, e2, bd, b1, b2);
+                        const double sv = Storage<ST>::round(v);
+                        const bool content = sv >= D.sparse_min, nz = sv != 0.0;
+                        const unsigned long long bc = __ballot(content), bz = __ballot(nz);
+                        if (lane == 0)
+                            D.litem[ns + rank_of(s_bm, s_rank, id)] =
+                                (bc ? 1 : 0) | (bz ? 2 : 0) | (has_bit(s_start, id) ? 0 : 4);
+                    }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -500,7 +554,7 @@ size_t accel_lds_bytes(const Dev &D, int *ncols, int *hc)
     *hc = 4 * mx;
     size_t b = sizeof(uint32_t) * (size_t)D.W * 3 + sizeof(int) * (size_t)(D.W + 1) + sizeof(int) * (size_t)nc * 2;
     b = (b + 15) & ~(size_t)15;
-    return b + sizeof(double) * 4 * 16 * (size_t)(*hc);
+    return b + sizeof(double) * 3 * 16 * (size_t)(*hc + 1) + sizeof(int32_t) * 4 * (size_t)(*hc / 16 + 1);
 }
 
 static AccelParams accel_params(const Dev &D, const double *fields, double *maps, int *bad, double qm, double dt,

@@ -460,6 +460,25 @@ def blob_mixture(seed=21454, n=(96, 96, 48), hot_fraction=0.4, cells=None, threa
     return w
 
 
+def lorentz_fields(ncell, seed=21455, B0=1e-8, vdrift=1e5, vpar=6e4, dt=None, qm=9.58e7):
+    """Seeded per-cell fields for an acceleration step: (ncell, 6) as Ex, Ey,
+    Ez [V/m], Bx, By, Bz [T], x fastest.  B of random direction and
+    0.5-1.5 B0; E = -Vd x B + E_par b with Vd perpendicular to B (normal
+    components of rms vdrift / sqrt(3)) and E_par moving a velocity by up to
+    vpar over dt (default dt: a gyration angle of 0.3 rad at B0)."""
+    if dt is None:
+        dt = 0.3 / (qm * B0)
+    rng = np.random.default_rng(seed)
+    b = rng.normal(size=(ncell, 3))
+    b /= np.linalg.norm(b, axis=1, keepdims=True)
+    B = b * (B0 * rng.uniform(0.5, 1.5, ncell))[:, None]
+    Vd = rng.normal(size=(ncell, 3)) * vdrift / math.sqrt(3.0)
+    Vd -= np.sum(Vd * b, axis=1, keepdims=True) * b
+    Epar = rng.uniform(-1.0, 1.0, ncell) * vpar / (qm * dt)
+    E = -np.cross(Vd, B) + Epar[:, None] * b
+    return np.concatenate([E, B], 1), dt
+
+
 def subbox_cells(n, lo, size, halo):
     """Local-cell indices (x-fastest, periodic wrap) of the box
     [lo - halo, lo + size + halo) of an n-box, in x-fastest order of the
