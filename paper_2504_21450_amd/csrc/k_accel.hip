@@ -169,37 +169,42 @@ __device__ __forceinline__ void col_edges(double amm, double am, double a0, doub
     }
 }
 
-// new average of cell i of a column of N cells moved by u -> alpha u + sigma
-// (inv_alpha = 1 / alpha): the mass of [(i - sigma)/alpha, (i + 1 - sigma)/alpha]
-// under the source parabolas (average a, edges l, r); a source cell covered
-// whole gives its average
-template <typename A, typename E>
-__device__ __forceinline__ double col_remap_cell(const A &a, const E &edges, int N, int i, double inv_alpha,
-                                                 double sigma)
+// mass of source cell j's limited parabola (average a0, edges l, r: CW84
+// eq. 1.10's profile) over [0, x] of the cell (0 <= x <= 1, cell units)
+__device__ __forceinline__ double col_head(double a0, double l, double r, double x)
 {
     constexpr double THIRD = 1.0 / 3.0;
-    const double lo = ((double)i - sigma) * inv_alpha, hi = ((double)i + 1.0 - sigma) * inv_alpha;
-    // source cells floor(lo) .. floor(hi) within the mesh (bounded before the
-    // conversion, so a pre-image far off the mesh gives an empty range)
+    const double a6 = 6.0 * (a0 - 0.5 * (l + r));
+    const double q = 0.5 * ((r - l) + a6);
+    return x * (l + x * (q - x * a6 * THIRD));
+}
+
+// new average of cell i of a column moved by u -> alpha u + sigma (inv_alpha =
+// 1 / alpha): the mass of its pre-image [(i - sigma)/alpha, (i + 1 - sigma)/alpha]
+// under the source parabolas, as the tail of the first source cell it meets
+// (the cell's average minus its head), the averages of the cells it covers
+// whole, and the head of the last; cells outside [base, base + ncell) (the
+// staged span) hold zero, and so does all of the mesh beyond it
+template <typename A, typename E>
+__device__ __forceinline__ double col_remap_cell(const A &a, const E &edges, int base, int ncell, int i,
+                                                 double inv_alpha, double sigma)
+{
+    double lo = ((double)i - sigma) * inv_alpha, hi = ((double)i + 1.0 - sigma) * inv_alpha;
+    if (!(hi > (double)base) || !(lo < (double)(base + ncell))) return 0.0;
+    lo = fmax(lo, (double)(base - 1));
+    hi = fmin(hi, (double)(base + ncell + 1));
     const double fl = floor(lo), fh = floor(hi);
-    const int j0 = fl < 0.0 ? 0 : (fl > (double)N ? N : (int)fl);
-    const int j1 = fh > (double)(N - 1) ? N - 1 : (fh < -1.0 ? -1 : (int)fh);
-    double m = 0.0;
-    for (int j = j0; j <= j1; j++) {
-        double xa = lo - (double)j, xb = hi - (double)j;
-        if (xa < 0.0) xa = 0.0;
-        if (xb > 1.0) xb = 1.0;
-        if (!(xb > xa)) continue;
-        const double a0 = a(j);
-        if (xa == 0.0 && xb == 1.0) {
-            m += a0;
-            continue;
-        }
-        double l, r;
-        edges(j, l, r);
-        const double a6 = 6.0 * (a0 - 0.5 * (l + r));
-        const double dA = r - l;
-        m += l * (xb - xa) + 0.5 * (dA + a6) * (xb * xb - xa * xa) - a6 * (xb * xb * xb - xa * xa * xa) * THIRD;
+    const int j0 = (int)fl, j1 = (int)fh;
+    const double xa = lo - fl, xb = hi - fh;
+    double l, r;
+    edges(j0, l, r);
+    const double a0 = a(j0);
+    if (j0 == j1) return col_head(a0, l, r, xb) - col_head(a0, l, r, xa);
+    double m = a0 - col_head(a0, l, r, xa);
+    for (int j = j0 + 1; j < j1; j++) m += a(j);
+    if (xb > 0.0) {
+        edges(j1, l, r);
+        m += col_head(a(j1), l, r, xb);
     }
     return m;
 }
@@ -522,7 +527,7 @@ __global__ __launch_bounds__(256) void k_accel(Dev D, AccelParams ap)
                     const int bd = lo + wv + 4 * u;
                     const int32_t sl = __builtin_amdgcn_readfirstlane(s_sl[u]);
                     const int32_t slot = sl >= 0 ? sl : -1 - sl;
-                    const double v = col_remap_cell(a, edges, N, 4 * bd + ld, inv_alpha, sigma);
+                    const double v = col_remap_cell(a, edges, base, ncell, 4 * bd + ld, inv_alpha, sigma);
                     Storage<ST>::store(D.pool, (int64_t)slot * BLK + lane, v);
                     if (last) {
                         const int32_t id = compose_id(D, d, e1, e2, bd, b1, b2);

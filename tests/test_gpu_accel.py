@@ -242,3 +242,29 @@ def test_velocity_mesh_beyond_the_kernel_is_refused():
                     np.zeros(0), block_capacity=64, ghost_block_capacity=64)
     EB = np.zeros((8, 6))
     assert p.accelerate_rc(1.0, QM, dev(EB)) == B.VL_ERR_ARG
+
+
+@pytest.mark.parametrize("storage", [B.VL_F32, B.VL_BF16])
+def test_reduced_storage_translation_and_acceleration_alternate(sparse_small, storage):
+    """Translation steps (per-line rounding ledger, re-injected at the next
+    shear along each axis) alternating with acceleration steps (which prune
+    blocks the ledger stores still name): every translation step balances
+    stored + pruned + ledger mass to 1e-12, every acceleration step's mass
+    change is what left the mesh plus what was pruned plus one rounding of
+    each value per remap; the run is the same bit for bit twice."""
+    w = sparse_small
+    print_case("translation and acceleration alternating, storage %d" % storage)
+    ulp = 2.0 ** -24 if storage == B.VL_F32 else 2.0 ** -9
+    finals = []
+    for _ in range(2):
+        p = gpu_partition(w, storage=storage)
+        for k in range(3):
+            s = run_gpu(p, w.dt, 1, stats=True)[0]
+            bal = s["mass_before"] - (s["mass_after"] + s["pruned_mass"] + s["ledger_mass"])
+            assert abs(bal) <= 1e-12 * s["mass_before"], bal / s["mass_before"]
+            a = p.accelerate(DT, QM, dev(random_fields(p.ncell, 800 + k)), stats=True)
+            rest = a["mass_before"] - a["mass_after"] - a["pruned_mass"]
+            assert abs(rest) <= 3 * ulp * a["mass_before"], rest / a["mass_before"]
+            assert np.min(p.export()[2]) >= 0.0
+        finals.append(p.export())
+    assert all(np.array_equal(x, y) for x, y in zip(*finals))
