@@ -119,6 +119,37 @@ __device__ __forceinline__ C clamp_min0(C x, C y)
         return fmax((C)0, fmin(x, y));
 }
 
+// limited slope of a cell (CW84 eq. 1.7-1.8) from its one-sided differences
+// dl, dr and central difference cen: cen limited to twice either one-sided
+// difference, zero at an extremum.  In FP32 it is minmod(cen, minmod(2 dl,
+// 2 dr)) with minmod(x, y) = median(x, y, 0) (the smaller magnitude when x
+// and y share a sign, else zero): two median-of-three instructions, the same
+// value as the general form (which FP64 keeps) up to the sign of a zero.
+template <typename C>
+__device__ __forceinline__ C limited_slope(C dl, C dr, C cen)
+{
+    if constexpr (std::is_same<C, float>::value) {
+        return __builtin_amdgcn_fmed3f(cen, __builtin_amdgcn_fmed3f(2.0f * dl, 2.0f * dr, 0.0f), 0.0f);
+    } else {
+        const C s2 = copysign((C)2.0, cen);
+        const C m = fmax((C)0, fmin(fmin(fabs(cen), s2 * dl), s2 * dr));
+        return copysign(m, cen);
+    }
+}
+
+// the monotonicity limiter's face offset x given the other side's offset y
+// (CW84 eq. 1.10 written on the offsets): x limited to twice y, zero unless
+// they share a sign (the extremum case); in FP32 minmod(x, 2 y), one
+// median-of-three instruction
+template <typename C>
+__device__ __forceinline__ C limited_offset(C x, C y)
+{
+    if constexpr (std::is_same<C, float>::value)
+        return __builtin_amdgcn_fmed3f(x, 2.0f * y, 0.0f);
+    else
+        return copysign(clamp_min0(fabs(x), copysign((C)2.0, x) * y), x);
+}
+
 // The FP64 update x of a cell (its carry included) in the storage type (a
 // negative sum, which only FP32 reconstruction rounding can leave, is stored
 // as zero).  nv receives the stored value in FP64, so the caller carries
@@ -185,7 +216,8 @@ __device__ __forceinline__ void block_store(__amdgpu_buffer_rsrc_t r, uint32_t o
 // The reconstruction is Colella & Woodward's, written in forms with fewer
 // operations that give the same values:
 //  * limited slope: copysign(max(0, min(|c|, 2 s dl, 2 s dr)), c) with
-//    c = (a+ - a-)/2 and s = sign(c) (zero unless dl and dr share a sign);
+//    c = (a+ - a-)/2 and s = sign(c) (zero unless dl and dr share a sign),
+//    in FP32 minmod(c, minmod(2 dl, 2 dr)) (limited_slope);
 //  * monotonicity limiter on the face offsets dL = a - aL, dR = aR - a: the
 //    two overshoot corrections of the limiter are dL' = min(|dL|, 2|dR|) and
 //    dR' = min(|dR|, 2|dL|) (with the sign of the side), the extremum case is
@@ -254,17 +286,13 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
             // slope of cell t-1
             const C dl = a1 - a2, dr = a - a1;
             const C cen = (C)0.5 * (a - a2);
-            const C s2 = copysign((C)2.0, cen);
-            const C m = fmax((C)0, fmin(fmin(fabs(cen), s2 * dl), s2 * dr));
-            const C da = copysign(m, cen);
+            const C da = limited_slope(dl, dr, cen);
             // face between t-2 and t-1
             const C face = a2 + (C)0.5 * (a1 - a2) - (da - da_prev) * (C)(1.0 / 6.0);
             // limited face offsets of cell t-2
             const C ai = a2;
             const C dL = ai - face_prev, dR = face - ai;
-            const C mL = clamp_min0(fabs(dL), copysign((C)2.0, dL) * dR);
-            const C mR = clamp_min0(fabs(dR), copysign((C)2.0, dR) * dL);
-            const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
+            const double dLp = (double)limited_offset(dL, dR), dRp = (double)limited_offset(dR, dL);
             const double aid = (double)ai;
             const double Fc = fma(P, dRp, fma(Q, dLp, c * aid));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
@@ -350,15 +378,11 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
             q[u] = fetch(t + PFV);
             const C dl = a1 - a2, dr = a - a1;
             const C cen = (C)0.5 * (a - a2);
-            const C s2 = copysign((C)2.0, cen);
-            const C m = fmax((C)0, fmin(fmin(fabs(cen), s2 * dl), s2 * dr));
-            const C da = copysign(m, cen);
+            const C da = limited_slope(dl, dr, cen);
             const C face = a2 + (C)0.5 * (a1 - a2) - (da - da_prev) * (C)(1.0 / 6.0);
             const C ai = a2;
             const C dL = ai - face_prev, dR = face - ai;
-            const C mL = clamp_min0(fabs(dL), copysign((C)2.0, dL) * dR);
-            const C mR = clamp_min0(fabs(dR), copysign((C)2.0, dR) * dL);
-            const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
+            const double dLp = (double)limited_offset(dL, dR), dRp = (double)limited_offset(dR, dL);
             const double aid = (double)ai;
             const double Fc = fma(P, dRp, fma(Q, dLp, c * aid));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
@@ -650,15 +674,11 @@ __device__ __forceinline__ void march_stream(const Dev &D, const uint32_t *X, co
             q[u] = fetch(src, fb + u);
             const C dl = a1 - a2, dr = a - a1;
             const C cen = (C)0.5 * (a - a2);
-            const C s2 = copysign((C)2.0, cen);
-            const C m = fmax((C)0, fmin(fmin(fabs(cen), s2 * dl), s2 * dr));
-            const C da = copysign(m, cen);
+            const C da = limited_slope(dl, dr, cen);
             const C face = a2 + (C)0.5 * dl - (da - da_prev) * (C)(1.0 / 6.0);
             const C ai = a2;
             const C dL = ai - face_prev, dR = face - ai;
-            const C mL = clamp_min0(fabs(dL), copysign((C)2.0, dL) * dR);
-            const C mR = clamp_min0(fabs(dR), copysign((C)2.0, dR) * dL);
-            const double dLp = (double)copysign(mL, dL), dRp = (double)copysign(mR, dR);
+            const double dLp = (double)limited_offset(dL, dR), dRp = (double)limited_offset(dR, dL);
             const double aid = (double)ai;
             const double Fc = fma(P, dRp, fma(Q, dLp, c * aid));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
