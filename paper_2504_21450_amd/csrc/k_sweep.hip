@@ -356,11 +356,12 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
     const uint32_t lane_off = (uint32_t)lane * BS;
     const uint32_t zslot = (uint32_t)D.trash;
 
-    auto fetch = [&](int t) -> C {
-        uint32_t sl = uniform_u32(srow[t]);
+    auto fetch_raw = [&](uint32_t raw) -> C {
+        uint32_t sl = uniform_u32(raw);
         sl = (sl & NEWFLAG) ? zslot : sl;
         return block_load<ST>(block_rsrc<ST>(D, sl), lane_off);
     };
+    auto fetch = [&](int t) -> C { return fetch_raw(srow[t]); };
 
     C a1 = 0, a2 = 0;
     double a3d = 0.0;
@@ -370,12 +371,20 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
     C q[PFV];
 #pragma unroll
     for (int u = 0; u < PFV; u++) q[u] = fetch(tb + u);
+    // slot-table entries of the cell fetched and the cell stored by the next
+    // iteration, read from LDS one iteration ahead so their latency is hidden
+    // behind a cell's arithmetic (the table is padded with ABSENT past L)
+    uint32_t f_next = srow[tb + PFV];
+    uint32_t s_next = srow[tb >= 3 ? tb - 3 : 0];
     for (int t0 = tb; t0 < te; t0 += PFV) {
 #pragma unroll
         for (int u = 0; u < PFV; u++) {
             const int t = t0 + u;
+            const uint32_t f_raw = f_next, s_raw = s_next;
+            f_next = srow[t + PFV + 1];
+            s_next = srow[t >= 2 ? t - 2 : 0];
             const C a = q[u];
-            q[u] = fetch(t + PFV);
+            q[u] = fetch_raw(f_raw);
             const C dl = a1 - a2, dr = a - a1;
             const C cen = (C)0.5 * (a - a2);
             const C da = limited_slope(dl, dr, cen);
@@ -387,7 +396,7 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
             const double Fc = fma(P, dRp, fma(Q, dLp, c * aid));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
             if (t >= 6 && t < L && t < te) {  // past te: the next segment's march
-                const uint32_t sl3 = uniform_u32(srow[t - 3]);
+                const uint32_t sl3 = uniform_u32(s_raw);
                 if (sl3 != ABSENT) {
                     const __amdgpu_buffer_rsrc_t dst = block_rsrc<ST>(D, sl3 & ~NEWFLAG);
                     double nv;
