@@ -287,13 +287,12 @@ __global__ __launch_bounds__(256) void k_accel(Dev D, AccelParams ap)
     // (byte offsets from the LDS array itself, so the compiler keeps these
     // pointers in the LDS address space): the block column being remapped,
     // averages and limited edges of 16 velocity columns of hc + 1 cells (odd
-    // stride: fewer bank conflicts), and per wavefront the slots of its blocks
+    // stride: fewer bank conflicts)
     const int hcs = ap.hc + 1;
     const int stage_off = (4 * (3 * W + (W + 1) + 2 * ap.ncols) + 15) & ~15;
     double *s_a = (double *)(smem + stage_off);
     double *s_l = s_a + 16 * hcs;
     double *s_r = s_l + 16 * hcs;
-    int32_t *s_sl = (int32_t *)(s_r + 16 * hcs) + wv * (ap.hc / 16 + 1);
 
     const int64_t q = blockIdx.x;
     const int x = (int)(q % D.n[0]), y = (int)((q / D.n[0]) % D.n[1]), z = (int)(q / ((int64_t)D.n[0] * D.n[1]));
@@ -473,28 +472,28 @@ __global__ __launch_bounds__(256) void k_accel(Dev D, AccelParams ap)
             const int b1 = col % nb1, b2 = col / nb1;
             const int ncell = 4 * (hi - lo + 1);
             const int nmine = (hi - lo >= wv) ? (hi - lo - wv) / 4 + 1 : 0;  // blocks of this wavefront
+            // lane u finds the slot of the wavefront's block u (at most
+            // hc / 16 + 1 < 64 of them): negative if the block was created in
+            // this remap (it reads as zero)
+            int32_t code = -1;
+            if (lane < nmine) {
+                const int32_t id = compose_id(D, d, e1, e2, lo + wv + 4 * lane, b1, b2);
+                const int32_t slot = D.lslot[ns + rank_of(s_bm, s_rank, id)];
+                code = has_bit(s_old, id) ? slot : -1 - slot;
+            }
             for (int u0 = 0; u0 < nmine; u0 += 8) {
-                int32_t sl[8];
-#pragma unroll
-                for (int u = 0; u < 8; u++) {
-                    sl[u] = -1;
-                    if (u0 + u < nmine) {
-                        const int32_t id = compose_id(D, d, e1, e2, lo + wv + 4 * (u0 + u), b1, b2);
-                        const int32_t slot = D.lslot[ns + rank_of(s_bm, s_rank, id)];
-                        sl[u] = __builtin_amdgcn_readfirstlane(has_bit(s_old, id) ? slot : -1 - slot);
-                    }
-                }
                 double v[8];
 #pragma unroll
-                for (int u = 0; u < 8; u++)
-                    v[u] = (u0 + u < nmine && sl[u] >= 0) ? Storage<ST>::load(D.pool, (int64_t)sl[u] * BLK + lane)
-                                                          : 0.0;
+                for (int u = 0; u < 8; u++) {
+                    v[u] = 0.0;
+                    if (u0 + u < nmine) {
+                        const int32_t sl = __builtin_amdgcn_readlane(code, u0 + u);
+                        if (sl >= 0) v[u] = Storage<ST>::load(D.pool, (int64_t)sl * BLK + lane);
+                    }
+                }
 #pragma unroll
                 for (int u = 0; u < 8; u++)
-                    if (u0 + u < nmine) {
-                        s_a[cc * hcs + 4 * (wv + 4 * (u0 + u)) + ld] = v[u];
-                        if (lane == 0) s_sl[u0 + u] = sl[u];
-                    }
+                    if (u0 + u < nmine) s_a[cc * hcs + 4 * (wv + 4 * (u0 + u)) + ld] = v[u];
             }
             __syncthreads();
             const int base = 4 * lo;
@@ -525,7 +524,7 @@ __global__ __launch_bounds__(256) void k_accel(Dev D, AccelParams ap)
                 const double sigma = col_sigma(D, row, d, e1, e2, 4 * b1 + l1, 4 * b2 + l2);
                 for (int u = 0; u < nmine; u++) {
                     const int bd = lo + wv + 4 * u;
-                    const int32_t sl = __builtin_amdgcn_readfirstlane(s_sl[u]);
+                    const int32_t sl = __builtin_amdgcn_readlane(code, u);
                     const int32_t slot = sl >= 0 ? sl : -1 - sl;
                     const double v = col_remap_cell(a, edges, base, ncell, 4 * bd + ld, inv_alpha, sigma);
                     Storage<ST>::store(D.pool, (int64_t)slot * BLK + lane, v);
@@ -559,7 +558,7 @@ size_t accel_lds_bytes(const Dev &D, int *ncols, int *hc)
     *hc = 4 * mx;
     size_t b = sizeof(uint32_t) * (size_t)D.W * 3 + sizeof(int) * (size_t)(D.W + 1) + sizeof(int) * (size_t)nc * 2;
     b = (b + 15) & ~(size_t)15;
-    return b + sizeof(double) * 3 * 16 * (size_t)(*hc + 1) + sizeof(int32_t) * 4 * (size_t)(*hc / 16 + 1);
+    return b + sizeof(double) * 3 * 16 * (size_t)(*hc + 1);
 }
 
 static AccelParams accel_params(const Dev &D, const double *fields, double *maps, int *bad, double qm, double dt,
