@@ -36,7 +36,8 @@ def oracle_subbox_step(w, lo):
 
 
 def local_indices(n, lo):
-    z, y, x = np.meshgrid(*[np.arange(lo[d], lo[d] + SUB[d]) for d in (2, 1, 0)], indexing="ij")
+    """Indices of the SUB cells from lo (periodic), x fastest."""
+    z, y, x = np.meshgrid(*[np.arange(lo[d], lo[d] + SUB[d]) % n[d] for d in (2, 1, 0)], indexing="ij")
     return (x + n[0] * (y + n[1] * z)).reshape(-1)
 
 
@@ -106,4 +107,48 @@ def test_fullsize_fp32_step_within_bound(full):
     print("sampled FP32 error %.3e" % err)
     resid = s["mass_before"] - (s["mass_after"] + s["pruned_mass"] + s["ledger_mass"])
     assert abs(resid) <= 1e-12 * s["mass_before"]
+    p.close()
+
+
+# two steps: the sampled 4^3 sub-box depends only on cells within 3 of it
+# after each step, so the oracle runs a 10^3 box around it (its true ghost
+# domain for the first step; for the second its own periodic images, which
+# are wrong only within 3 cells of that box's faces) and the inner 4^3 is
+# compared
+ORIGINS_2 = [(0, 0, 0), (62, 1, 30), (13, 50, 7), (31, 31, 16), (5, 40, 29), (48, 9, 3), (20, 63, 21), (57, 27, 14)]
+
+
+def oracle_subbox_two_steps(w, lo):
+    big = tuple(s + 6 for s in SUB)
+    blo = tuple((lo[d] - 3) % w.n[d] for d in range(3))
+    cells = W.subbox_cells(w.n, blo, big, 3)
+    off, ids, f = W.take_cells(w.offsets, w.ids, w.f, cells)
+    o = OraclePartition(big, w.nblk, w.dx, w.vmin, w.dv, w.order, w.sparse_min, w.vbuffer)
+    o.load_padded(off, ids, f)
+    oracle.lib().vlo_mark_ghosts_valid(o._h)
+    o.step(w.dt)
+    o.fill_ghosts()
+    o.step(w.dt)
+    bo, bi, bf = o.export_local()
+    # the inner SUB cells of the 10^3 box, in x-fastest order
+    inner = local_indices(big, (3, 3, 3))
+    return W.take_cells(bo, bi, bf, inner)
+
+
+def test_fullsize_two_steps_match_oracle_on_eight_subboxes(full):
+    w = full
+    print_case("full size FP64, two coalesced steps, eight sampled sub-boxes")
+    p = B.Partition.from_workload(w, slack=1.4)
+    for _ in range(2):
+        p.fill_ghosts()
+        p.step(w.dt, B.VL_COALESCED)
+    worst = 0.0
+    for lo in ORIGINS_2:
+        got = p.export_cells(local_indices(w.n, lo))
+        want = oracle_subbox_two_steps(w, lo)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), ("lists differ", lo)
+        err = np.max(np.abs(got[2] - want[2])) / np.max(np.abs(want[2]))
+        worst = max(worst, err)
+    print("two steps, eight sub-boxes: worst error %.3e" % worst)
+    assert worst <= 1e-12
     p.close()
