@@ -29,7 +29,8 @@
 //   * the workgroup remaps one block column at a time: it stages the column
 //     in LDS (16 velocity columns x its span, missing blocks as zero; eight
 //     blocks' loads in flight per wavefront), the limited parabola edges of
-//     every cell once, then the new averages, writing every block of the
+//     every cell once (runs of consecutive cells per thread, each slope
+//     computed once), then the new averages, writing every block of the
 //     span, 64 lanes = the block's 64 cells, so loads and stores are
 //     coalesced;
 //   * the last remap leaves per list entry the flags the pruning reads:
@@ -146,14 +147,13 @@ __device__ __forceinline__ double col_slope(double am, double a0, double ap)
     return (dr * dl > 0.0) ? copysign(m, central) : 0.0;
 }
 
-// limited parabola edges (l, r) of a cell from the averages of cells
-// j-2 .. j+2 (CW84 eq. 1.6 faces from the limited slopes, then the eq. 1.10
-// limiter)
-__device__ __forceinline__ void col_edges(double amm, double am, double a0, double ap, double app, double &l,
-                                          double &r)
+// limited parabola edges (l, r) of a cell from its average a0, its
+// neighbours' am, ap and the limited slopes dm, d0, dp of cells j-1, j, j+1
+// (CW84 eq. 1.6 faces, then the eq. 1.10 limiter)
+__device__ __forceinline__ void col_edges(double am, double a0, double ap, double dm, double d0, double dp,
+                                          double &l, double &r)
 {
     constexpr double SIXTH = 1.0 / 6.0;
-    const double dm = col_slope(amm, am, a0), d0 = col_slope(am, a0, ap), dp = col_slope(a0, ap, app);
     l = am + 0.5 * (a0 - am) - (d0 - dm) * SIXTH;
     r = a0 + 0.5 * (ap - a0) - (dp - d0) * SIXTH;
     if ((r - a0) * (a0 - l) <= 0.0) {
@@ -497,15 +497,32 @@ __global__ __launch_bounds__(256) void k_accel(Dev D, AccelParams ap)
             }
             __syncthreads();
             const int base = 4 * lo;
-            for (int t = tid; t < 16 * ncell; t += 256) {
-                const int tc = t & 15, j = t >> 4;
+            {
+                // thread (velocity column tc, run q) takes the run of
+                // consecutive cells [j0, j1) of its column with a sliding
+                // window, so each cell's limited slope is computed once
+                const int tc = tid & 15, q = tid >> 4;
+                const int per = (ncell + 15) >> 4;
+                const int j0 = q * per, j1 = min(j0 + per, ncell);
                 const double *ac = s_a + tc * hcs;
-                const double amm = j >= 2 ? ac[j - 2] : 0.0, am = j >= 1 ? ac[j - 1] : 0.0, a0 = ac[j];
-                const double ap = j + 1 < ncell ? ac[j + 1] : 0.0, app = j + 2 < ncell ? ac[j + 2] : 0.0;
-                double l, r;
-                col_edges(amm, am, a0, ap, app, l, r);
-                s_l[tc * hcs + j] = l;
-                s_r[tc * hcs + j] = r;
+                auto A = [&](int j) -> double { return (j >= 0 && j < ncell) ? ac[j] : 0.0; };
+                if (j0 < j1) {
+                    double am = A(j0 - 1), a0 = A(j0), ap = A(j0 + 1);
+                    double dm = col_slope(A(j0 - 2), am, a0), d0 = col_slope(am, a0, ap);
+                    for (int j = j0; j < j1; j++) {
+                        const double app = A(j + 2);
+                        const double dp = col_slope(a0, ap, app);
+                        double l, r;
+                        col_edges(am, a0, ap, dm, d0, dp, l, r);
+                        s_l[tc * hcs + j] = l;
+                        s_r[tc * hcs + j] = r;
+                        am = a0;
+                        a0 = ap;
+                        ap = app;
+                        dm = d0;
+                        d0 = dp;
+                    }
+                }
             }
             __syncthreads();
             {
