@@ -285,6 +285,17 @@ def run(p, w, storage, mode, steps, warmup, tune_steps, variant=None, graph_step
         out["graph"] = {"steps": graph_steps, "ms_per_step": 1e3 * ge / graph_steps,
                         "value": 3 * 0.5 * (b0 + b1) * 64 * graph_steps / ge}
         log("graph replay: %.2f ms/step" % (1e3 * ge / graph_steps))
+    # one more step (untimed) with the FP64 mass statistics: the mass held in
+    # f and the mass in f plus the rounding ledger, each against the mass
+    # before the step less what the pruning removed
+    if mode == B.VL_COALESCED:
+        p.fill_ghosts()
+    st = p.step(w.dt, mode, stats=True)
+    m0 = st["mass_before"]
+    out["mass_one_step"] = {
+        "stored_only_rel": (st["mass_after"] + st["pruned_mass"] - m0) / m0,
+        "stored_plus_ledger_rel": (st["mass_after"] + st["pruned_mass"] + st["ledger_mass"] - m0) / m0,
+        "pruned_rel": st["pruned_mass"] / m0}
     return out
 
 
@@ -488,6 +499,7 @@ def main():
     }
     if "graph" in r:
         out["graph"] = r["graph"]
+    out["mass_one_step"] = r["mass_one_step"]
     if args.accel_steps > 0:
         acc_n = (n[0], n[1], max(1, n[2] // 2)) if mixture else n
         acc = accel_run(args.workload, acc_n, args.hot, storage, args.accel_steps)

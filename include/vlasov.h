@@ -233,7 +233,9 @@ int vl_accelerate(vl_partition *p, double dt, double qm, const double *dev_field
  * order); in VL_PER_SWEEP mode the per-direction refreshes and shears.  Each
  * step gives the same state bit for bit as vl_fill_ghosts (coalesced mode)
  * plus vl_translate_step.  The graphs are cached per starting list region
- * and re-recorded when dt, mode, shear variant or Courant override change;
+ * and, in FP32/BF16 storage, per rotation of the per-line ledger stores (a
+ * step swaps them, repeating every four steps), and re-recorded when dt,
+ * mode, shear variant or Courant override change;
  * recording uses a private stream, replays go to the partition's stream.
  * The recorded ghost update uses the sources of the last vl_fill_ghosts_from
  * if there was one (required when desc.edges is set), else periodic images.

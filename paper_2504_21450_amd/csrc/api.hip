@@ -68,8 +68,11 @@ Layout make_layout(const vl_desc *d)
     L.nlocal = (int64_t)d->n[0] * d->n[1] * d->n[2];
     L.nghost = L.N - L.nlocal;
     const int64_t lcap = d->block_capacity, gcap = d->ghost_block_capacity;
-    L.LA = lcap + lcap / 2 + 32 * L.nlocal;
-    L.LG = gcap + gcap / 2 + 32 * L.nghost;
+    // list regions: the lists as written (25 % + 32 slack per cell) and room
+    // for the lists that outgrow them within a step and move to the region's
+    // end (at most once per cell and shear, again with 25 % + 32 slack)
+    L.LA = lcap + 3 * (lcap / 4) + 64 * L.nlocal;
+    L.LG = gcap + 3 * (gcap / 4) + 64 * L.nghost;
     L.row_cap = lcap + gcap + 64;
     const int64_t tot = lcap + gcap;
     // one item per block of a pencil's union: at most one per (cell, block)

@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
             if (req == 0) continue;
             const int have = s_cnt[i] + s_new[i];
             if (have + req <= s_cap[i]) continue;
-            const int ncap = (have + req) + (have + req) / 2 + 32;
+            const int ncap = (have + req) + (have + req) / 4 + 32;  // the slack of a fresh list
             const int reg = local_pencil ? pp.cur : 2;
             unsigned long long *top = local_pencil ? &D.ctl->list_top[pp.cur] : &D.ctl->ghost_list_top;
             const unsigned long long nb0 = atomicAdd(top, (unsigned long long)ncap);
