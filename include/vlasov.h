@@ -276,7 +276,10 @@ int vl_local_block_count(vl_partition *p, int64_t *out);
 
 /* Copy the local cells to host memory as CSR (ids ascending per cell, values
  * converted to FP64): cell_offsets[ncell+1], block_ids[cap_blocks],
- * f[64*cap_blocks].  VL_ERR_ARG if cap_blocks is too small.  Synchronises. */
+ * f[64*cap_blocks].  VL_ERR_ARG if cap_blocks is too small.  Synchronises.
+ * The per-line rounding ledger of FP32/BF16 storage is not part of the
+ * exported state: a partition initialised from it starts with an empty
+ * ledger (its stored mass is what f holds). */
 int vl_export_state(vl_partition *p, int64_t *cell_offsets, int32_t *block_ids, double *f,
                     int64_t cap_blocks);
 
