@@ -26,7 +26,6 @@ struct Layout {
         pencnt, pensum, ctl, cover, cellred, red, cellcnt, mom, lg_ids[4], lg_res[4], lg_kfirst[4],
         lg_kcnt[4], lg_src, accel, total;
     int64_t N, nlocal, nghost, LA, LG, row_cap, item_cap, pen_cap, mom_parts, lg_cap;
-    int tab_stride;
     int wlmax, cover_stride;
 };
 
@@ -109,8 +108,7 @@ Layout make_layout(const vl_desc *d)
     L.cellcnt = o; o = align_up(o + (size_t)L.nlocal * 4);
     // moments: a split cell has fewer than 2 cnt / MOM_CHUNK chunks
     L.mom_parts = 2 * lcap / MOM_CHUNK + 64;
-    L.tab_stride = 2 * std::max(d->nblk[0], std::max(d->nblk[1], d->nblk[2])) - 1;
-    L.mom = o;     o = align_up(o + (size_t)moments_scratch_bytes(L.nlocal, L.mom_parts, L.mom_parts, L.tab_stride));
+    L.mom = o;     o = align_up(o + (size_t)moments_scratch_bytes(L.nlocal, L.mom_parts, L.mom_parts));
     // per-line mass ledger (reduced storage): three stores, one per shear
     // axis, and a fourth that the next shear writes; each holds a shear's
     // items (block id and FP64 residual) and per pencil key its item range
@@ -512,7 +510,7 @@ int vl_init_partition(const vl_desc *d, void *dev_workspace, size_t ws_bytes, vo
         g.kfirst = on ? (int32_t *)(w + L.lg_kfirst[k]) : nullptr;
         g.kcnt = on ? (int32_t *)(w + L.lg_kcnt[k]) : nullptr;
     }
-    p->mom = carve_moments_scratch(w + L.mom, L.nlocal, L.mom_parts, L.mom_parts, L.tab_stride, MOM_CHUNK);
+    p->mom = carve_moments_scratch(w + L.mom, L.nlocal, L.mom_parts, L.mom_parts, MOM_CHUNK);
     // the fixed scratch array of vl_moments_static on this device (its
     // address, taken once per device)
     p->mom_static = nullptr;
@@ -882,14 +880,14 @@ int vl_moments_static(vl_partition *p, double *dev_n, double *dev_V3, double *de
     if (!p->mom_static) return VL_ERR_HIP;
     // the chunk size that keeps every possible split within the array: the
     // workspace's when it fits, else larger
-    const int64_t fixed = moments_scratch_bytes(L.nlocal, 0, 0, L.tab_stride);
+    const int64_t fixed = moments_scratch_bytes(L.nlocal, 0, 0);
     const int64_t per_part = 80 + 8;
     if (fixed + 64 * per_part + 1024 > STATIC_MOMENTS_SCRATCH_BYTES) return VL_ERR_SCRATCH;
     const int64_t parts = (STATIC_MOMENTS_SCRATCH_BYTES - fixed - 1024) / per_part;
     int64_t chunk = MOM_CHUNK;
     if (2 * D.lcap / chunk + 64 > parts) chunk = (2 * D.lcap + parts - 65) / (parts - 64);
     if (chunk > (int64_t)1 << 30) return VL_ERR_SCRATCH;
-    const MomScratch M = carve_moments_scratch(p->mom_static, L.nlocal, parts, parts, L.tab_stride, (int)chunk);
+    const MomScratch M = carve_moments_scratch(p->mom_static, L.nlocal, parts, parts, (int)chunk);
     {
         ProfScope ps(p, K_OTHER);
         launch_moments(D, M, dev_n, dev_V3, dev_P6, p->stream);

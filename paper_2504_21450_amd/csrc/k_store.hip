@@ -345,7 +345,8 @@ void launch_cell_counts(const Dev &D, hipStream_t st)
 // writes the cell's moments; the units of a split cell leave ten partial sums
 // each, which the cell's combine pass adds in chunk order (the same result in
 // every run).  Per block the lanes add f, f c, f c c^T with c the block
-// centre's offset from R (uniform over the block, read from a small table);
+// centre's offset from R (uniform over the block, computed from the two
+// blocks' packed coordinates);
 // each lane's offset o within the block enters once at the end:
 //   sum f (c + o) = S1c + o S0,  sum f (c+o)(c+o)^T = S2c + S1c o^T + o S1c^T + S0 o o^T.
 // ---------------------------------------------------------------------------
@@ -395,17 +396,12 @@ __device__ inline void reference_velocity(const Dev &D, int32_t idR, int cnt, do
 }
 
 // counters to zero (a kernel, not a memset, so graph captures replay it
-// faithfully) and the block-centre offset table
-__global__ __launch_bounds__(256) void k_mom_reset(Dev D, MomScratch M)
+// faithfully)
+__global__ __launch_bounds__(256) void k_mom_reset(MomScratch M)
 {
     if (threadIdx.x == 0) {
         M.ctr[0] = 0ull;
         M.ctr[1] = 0ull;
-    }
-    const int tmid = (M.tab_stride - 1) / 2;
-    for (int i = threadIdx.x; i < 3 * M.tab_stride; i += 256) {
-        const int a = i / M.tab_stride, k = i % M.tab_stride - tmid;
-        M.tab[i] = (double)(4 * k) * D.dv[a];
     }
 }
 
@@ -434,21 +430,19 @@ __global__ __launch_bounds__(256) void k_mom_plan(Dev D, MomScratch M)
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_mom_units(Dev D, MomScratch M, const double *__restrict__ tab,
-                                                   double *dn, double *dV, double *dP)
+__global__ __launch_bounds__(256) void k_mom_units(Dev D, MomScratch M, double *dn, double *dV, double *dP)
 {
     if (failed(D)) return;
     const int lane = threadIdx.x & 63;
-    // the wavefront's index, made visibly uniform so the unit's cell, its
-    // metadata and the offset table are read with scalar loads
+    // the wavefront's index, made visibly uniform so the unit's cell and its
+    // metadata are read with scalar loads
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nunits = D.nlocal + (int64_t)min(M.ctr[1], (unsigned long long)M.cap_extra);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     using T = typename Storage<ST>::T;
     constexpr int NF = ST == VL_F64 ? 8 : 16;  // raw words of NF blocks in flight
     const T *pool = (const T *)D.pool;
-    const int tstride = M.tab_stride;          // offsets table: axis a, k in [-(tstride-1)/2, ..]
-    const int tmid = (tstride - 1) / 2;
+    const double dvx = D.dv[0], dvy = D.dv[1], dvz = D.dv[2];
     // the lane's velocity offset from its block's centre
     const double o[3] = {((lane & 3) - 1.5) * D.dv[0], (((lane >> 2) & 3) - 1.5) * D.dv[1],
                          ((lane >> 4) - 1.5) * D.dv[2]};
@@ -475,10 +469,11 @@ __global__ __launch_bounds__(256) void k_mom_units(Dev D, MomScratch M, const do
         const int b0 = j * M.chunk, b1 = min(cnt, b0 + M.chunk);
         double s0 = 0.0, s1[3] = {0.0, 0.0, 0.0}, s2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         auto acc = [&](double f, int32_t pk) {
-            // block centre offset from R: uniform, from the table
-            const double cx = tab[(pk & 1023) - (pkR & 1023) + tmid];
-            const double cy = tab[tstride + ((pk >> 10) & 1023) - ((pkR >> 10) & 1023) + tmid];
-            const double cz = tab[2 * tstride + (pk >> 20) - (pkR >> 20) + tmid];
+            // block centre offset from R, 4 k dv per axis (uniform; k from the
+            // packed block coordinates in scalar registers)
+            const double cx = (double)(4 * ((pk & 1023) - (pkR & 1023))) * dvx;
+            const double cy = (double)(4 * (((pk >> 10) & 1023) - ((pkR >> 10) & 1023))) * dvy;
+            const double cz = (double)(4 * ((pk >> 20) - (pkR >> 20))) * dvz;
             const double fx = f * cx, fy = f * cy, fz = f * cz;
             s0 += f;
             s1[0] += fx;
@@ -571,14 +566,14 @@ template <int ST>
 static void launch_mom_units(const Dev &D, const MomScratch &M, double *dn, double *dV, double *dP, hipStream_t st)
 {
     static const unsigned g = resident_groups(k_mom_units<ST>);
-    hipLaunchKernelGGL(k_mom_units<ST>, dim3(g), dim3(256), 0, st, D, M, (const double *)M.tab, dn, dV, dP);
+    hipLaunchKernelGGL(k_mom_units<ST>, dim3(g), dim3(256), 0, st, D, M, dn, dV, dP);
 }
 
 void launch_moments(const Dev &D, const MomScratch &M, double *dn, double *dV, double *dP, hipStream_t st)
 {
     if (D.nlocal <= 0) return;
     const dim3 gc((unsigned)((D.nlocal + 255) / 256));
-    hipLaunchKernelGGL(k_mom_reset, dim3(1), dim3(256), 0, st, D, M);
+    hipLaunchKernelGGL(k_mom_reset, dim3(1), dim3(256), 0, st, M);
     hipLaunchKernelGGL(k_mom_plan, gc, dim3(256), 0, st, D, M);
     switch (D.storage) {
     case VL_F64: launch_mom_units<VL_F64>(D, M, dn, dV, dP, st); break;
@@ -613,14 +608,13 @@ int static_moments_scratch(void **ptr)
     return 0;
 }
 
-int64_t moments_scratch_bytes(int64_t nlocal, int64_t parts, int64_t extras, int tab_stride)
+int64_t moments_scratch_bytes(int64_t nlocal, int64_t parts, int64_t extras)
 {
     auto al = [](int64_t v) { return (v + 255) / 256 * 256; };
-    return al(16) + al(nlocal * 4) + al(nlocal * 8) + al(parts * 80) + al(extras * 8) + al((int64_t)tab_stride * 24);
+    return al(16) + al(nlocal * 4) + al(nlocal * 8) + al(parts * 80) + al(extras * 8);
 }
 
-MomScratch carve_moments_scratch(void *base, int64_t nlocal, int64_t parts, int64_t extras, int tab_stride,
-                                 int chunk)
+MomScratch carve_moments_scratch(void *base, int64_t nlocal, int64_t parts, int64_t extras, int chunk)
 {
     auto al = [](int64_t v) { return (v + 255) / 256 * 256; };
     char *w = (char *)base;
@@ -629,12 +623,10 @@ MomScratch carve_moments_scratch(void *base, int64_t nlocal, int64_t parts, int6
     M.cell_base = (int32_t *)w;               w += al(nlocal * 4);
     M.cell_mass = (double *)w;                w += al(nlocal * 8);
     M.part = (double *)w;                     w += al(parts * 80);
-    M.extra = (int2 *)w;                      w += al(extras * 8);
-    M.tab = (double *)w;
+    M.extra = (int2 *)w;
     M.cap_part = parts;
     M.cap_extra = extras;
     M.chunk = chunk;
-    M.tab_stride = tab_stride;
     return M;
 }
 

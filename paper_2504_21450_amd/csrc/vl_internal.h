@@ -230,21 +230,18 @@ void launch_reduce(const Dev &D, const double *in, int64_t n, double *out, hipSt
 // scratch of the moments: per local cell the first partial slot of a split
 // cell (-1: one chunk) and the cell's mass; per chunk of a split cell ten
 // partial sums; the further chunks (cell, chunk) as work units; two counters
-// and the table of block-centre offsets 4 k dv_a (k in [-tmid, tmid])
 struct MomScratch {
     unsigned long long *ctr;
     int32_t *cell_base;
     double *cell_mass;
     double *part;
     int2 *extra;
-    double *tab;
     int64_t cap_part, cap_extra;
-    int chunk, tab_stride;
+    int chunk;
 };
 constexpr int MOM_CHUNK = 1024;  // blocks per moments work unit (cells with more are split)
-int64_t moments_scratch_bytes(int64_t nlocal, int64_t parts, int64_t extras, int tab_stride);
-MomScratch carve_moments_scratch(void *base, int64_t nlocal, int64_t parts, int64_t extras, int tab_stride,
-                                 int chunk);
+int64_t moments_scratch_bytes(int64_t nlocal, int64_t parts, int64_t extras);
+MomScratch carve_moments_scratch(void *base, int64_t nlocal, int64_t parts, int64_t extras, int chunk);
 void launch_moments(const Dev &D, const MomScratch &M, double *dn, double *dV, double *dP, hipStream_t st);
 // the fixed device array of the allocation-free moments entry point: its
 // address on the current device (taken once per device), and its size
