@@ -42,30 +42,43 @@ struct PlanParams {
 
 __device__ inline int popc(uint32_t v) { return __popc(v); }
 
+// threads and wavefronts of a planner workgroup, and its LDS budget: four
+// workgroups fit a compute unit's 160 KiB (and its registers), and a
+// pencil's union is taken in chunks of as many block ids as the budget holds
+// (larger chunks in fewer, larger workgroups were slower on the mixture)
+constexpr int PNT = 256;
+constexpr int PNW = PNT / 64;
+constexpr size_t PLAN_LDS_BUDGET = 34 * 1024;
+
 // cells of a pencil rounded up to a multiple of 8 (LDS array length)
 __host__ __device__ inline int plan_cells(int L) { return (L + 7) & ~7; }
 
-// exclusive scan of a[0..n) in place (LDS) by 256 threads; returns the total
-__device__ int block_scan_excl(int *a, int n, int *s_tmp)
+// exclusive scan of a[0..n) in place (LDS) by the workgroup: each thread
+// sums a run of consecutive entries, the runs' sums are scanned within each
+// wavefront by shuffles and across the wavefronts through s_w[PNW]; returns
+// the total
+__device__ int block_scan_excl(int *a, int n, int *s_w)
 {
-    const int tid = threadIdx.x;
-    const int per = (n + 255) / 256;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per = (n + PNT - 1) / PNT;
     const int b = min(tid * per, n), e = min(b + per, n);
     int sum = 0;
     for (int i = b; i < e; i++) sum += a[i];
-    s_tmp[tid] = sum;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the 256 partial sums
-    for (int o = 1; o < 256; o <<= 1) {
-        int v = (tid >= o) ? s_tmp[tid - o] : 0;
-        __syncthreads();
-        s_tmp[tid] += v;
-        __syncthreads();
+    int incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
     }
-    int run = s_tmp[tid] - sum;
-    const int total = s_tmp[255];
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    int run = incl - sum, total = 0;
+    for (int w = 0; w < PNW; w++) {
+        const int t = s_w[w];
+        run += (w < wave) ? t : 0;
+        total += t;
+    }
     for (int i = b; i < e; i++) {
-        int v = a[i];
+        const int v = a[i];
         a[i] = run;
         run += v;
     }
@@ -73,25 +86,22 @@ __device__ int block_scan_excl(int *a, int n, int *s_tmp)
     return total;
 }
 
-__device__ inline long long block_sum_ll(long long v, long long *s_tmp)
+__device__ inline long long block_sum_ll(long long v, long long *s_w)
 {
-    const int tid = threadIdx.x;
-    s_tmp[tid] = v;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) s_tmp[tid] += s_tmp[tid + o];
-        __syncthreads();
-    }
-    long long r = s_tmp[0];
+    long long r = 0;
+    for (int w = 0; w < PNW; w++) r += s_w[w];
     __syncthreads();
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
+__global__ __launch_bounds__(PNT) void k_plan(Dev D, PlanParams pp)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_tmp[256];
-    __shared__ long long s_ll[256];
+    __shared__ int s_tmp[PNW];
+    __shared__ long long s_ll[PNW];
     __shared__ unsigned long long s_base[4];  // (unused), row, new-slot bases, status
     __shared__ long long s_ibp;               // the pencil's first item
     const int tid = threadIdx.x;
@@ -115,9 +125,11 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     uint32_t *s_pres = (uint32_t *)q; q += sizeof(uint32_t) * R * WL;
     uint32_t *s_newb = (uint32_t *)q; q += sizeof(uint32_t) * R * WL;
     int *s_id = (int *)q; q += sizeof(int) * R;
-    int *s_ai = (int *)q; q += sizeof(int) * (R + 1);  // item prefix
     int *s_ro = (int *)q; q += sizeof(int) * (R + 1);  // row prefix
     int *s_np = (int *)q; q += sizeof(int) * (R + 1);  // new-block prefix
+    // per block of the chunk and mask word w: the cells of its row in words
+    // before w (at most 224), or 255 for a block no updated cell holds
+    uint8_t *s_cum = (uint8_t *)q; q += (size_t)R * WL;
 
     const int p = blockIdx.x;
     const int t1 = pp.lo1 + p % pp.n1;
@@ -132,7 +144,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     const bool last = pp.sidx == 2;  // last shear of the step: record list entry -> item
 
     // 0. cell metadata
-    for (int i = tid; i < L; i += 256) {
+    for (int i = tid; i < L; i += PNT) {
         const int64_t c = base + sd * i;
         s_cs[i] = D.lstart[c];
         s_cnt[i] = D.lcount[c];
@@ -142,7 +154,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         s_pos[i] = 0;
         s_srt[i] = D.lsorted[c];
     }
-    for (int w = tid; w < W; w += 256) s_bm[w] = 0u;
+    for (int w = tid; w < W; w += PNT) s_bm[w] = 0u;
     if (tid == 0) s_base[3] = failed(D) ? 1ull : 0ull;
     __syncthreads();
     if (s_base[3]) return;  // fail-stop, one decision per workgroup (nothing written yet)
@@ -165,11 +177,11 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     {
         int32_t nxt[4] = {-1, -1, -1, -1};
         if (wave < L) load_ids(wave, lane, nxt);
-        for (int i = wave; i < L; i += 4) {
+        for (int i = wave; i < L; i += PNW) {
             int32_t ids[4];
 #pragma unroll
             for (int k = 0; k < 4; k++) ids[k] = nxt[k];
-            if (i + 4 < L) load_ids(i + 4, lane, nxt);
+            if (i + PNW < L) load_ids(i + PNW, lane, nxt);
             file_ids(ids);
             for (int e0 = lane + 256; e0 < s_cnt[i]; e0 += 256) {  // lists longer than 256
                 load_ids(i, e0, ids);
@@ -179,7 +191,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     }
     __syncthreads();
     // 2. ranks
-    for (int w = tid; w < W; w += 256) s_rank[w] = popc(s_bm[w]);
+    for (int w = tid; w < W; w += PNT) s_rank[w] = popc(s_bm[w]);
     __syncthreads();
     const int U = block_scan_excl(s_rank, W, s_tmp);
     // the pencil's items: item first + r for the block of union rank r
@@ -220,7 +232,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
 
     for (int r0 = 0; r0 < U; r0 += R) {
         const int rn = min(R, U - r0);
-        for (int k = tid; k < rn * WL; k += 256) s_pres[k] = 0u;
+        for (int k = tid; k < rn * WL; k += PNT) s_pres[k] = 0u;
         __syncthreads();
         // presence masks of this chunk.  Ranks grow along the ascending
         // prefix of a list, so a cell's prefix entries in the chunk are the
@@ -241,7 +253,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         };
         int32_t nid[4] = {-1, -1, -1, -1}, ntail = -1;
         if (wave < L) load_run(wave, nid, ntail);
-        for (int i = wave; i < L; i += 4) {
+        for (int i = wave; i < L; i += PNW) {
             const int cnt = s_cnt[i], srt = s_srt[i];
             const int32_t *lst = D.lid + s_cs[i];
             const uint32_t cbit = 1u << (i & 31);
@@ -250,7 +262,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
 #pragma unroll
             for (int u = 0; u < 4; u++) ids[u] = nid[u];
             const int32_t tail0 = ntail;
-            if (i + 4 < L) load_run(i + 4, nid, ntail);
+            if (i + PNW < L) load_run(i + PNW, nid, ntail);
             // 256 entries are loaded at once (the run usually continues) and
             // taken 64 at a time until the first one beyond the chunk
             int pos = s_pos[i];
@@ -265,16 +277,22 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                     }
                 }
                 first = false;
+                // the ranks of all four groups are read before any is filed,
+                // so their LDS reads overlap
+                int kq[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int32_t id = ids[u];
+                    const int w = id >= 0 ? id >> 5 : 0;
+                    const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
+                    kq[u] = id >= 0 ? k : rn;
+                }
                 int taken = 0;
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                     if (more) {
                         const int32_t id = ids[u];
-                        int k = rn;
-                        if (id >= 0) {
-                            const int w = id >> 5;
-                            k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
-                        }
+                        const int k = kq[u];
                         const bool in = k < rn;
                         if (in) {
                             atomicOr(&s_pres[k * WL + cw], cbit);
@@ -301,7 +319,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         }
         __syncthreads();
         // growth and per-block counts
-        for (int k = tid; k < rn; k += 256) {
+        for (int k = tid; k < rn; k += PNT) {
             uint32_t P[MAXWL], G[MAXWL];
 #pragma unroll
             for (int w = 0; w < MAXWL; w++) P[w] = (w < WL) ? s_pres[k * WL + w] : 0u;
@@ -339,9 +357,18 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                     }
                 }
             }
-            s_ai[k] = active ? 1 : 0;
             s_ro[k] = active ? rowlen : 0;
             s_np[k] = active ? nnew : 0;
+            {
+                int run = 0;
+#pragma unroll
+                for (int w = 0; w < MAXWL; w++) {
+                    if (w < WL) {
+                        s_cum[k * WL + w] = active ? (uint8_t)run : (uint8_t)255;
+                        run += popc(P[w] | G[w]);
+                    }
+                }
+            }
             if (active) {
                 st_upd += upd;
                 st_read += rd;
@@ -353,7 +380,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         // list to a larger place at the end of its list region: the places
         // are taken per cell, then each wavefront copies the lists of its
         // cells (coalesced; the old places are not reused within the step)
-        for (int i = tid; i < L; i += 256) {
+        for (int i = tid; i < L; i += PNT) {
             s_mvn[i] = 0;
             const int req = s_req[i];  // cleared when the cell's new entries are written
             if (req == 0) continue;
@@ -377,7 +404,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
             D.lcapa[c] = ncap;
         }
         __syncthreads();
-        for (int i = wave; i < L; i += 4) {
+        for (int i = wave; i < L; i += PNW) {
             const int n = s_mvn[i];
             if (n == 0) continue;
             const int64_t from = s_mvsrc[i], to = s_cs[i];
@@ -388,11 +415,9 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
             }
         }
         __syncthreads();
-        const int nact = block_scan_excl(s_ai, rn, s_tmp);
         const int nrow = block_scan_excl(s_ro, rn, s_tmp);
         const int nnew = block_scan_excl(s_np, rn, s_tmp);
         if (tid == 0) {
-            s_ai[rn] = nact;
             s_ro[rn] = nrow;
             s_np[rn] = nnew;
             unsigned long long err = 0;
@@ -429,13 +454,13 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         const bool alloc_failed = (s_base[3] & 2) != 0;
 
         // items and new blocks
-        for (int k = tid; k < rn; k += 256) {
+        for (int k = tid; k < rn; k += PNT) {
             const int64_t it = ibp + r0 + k;
             if (pp.lg.src && it < pp.lg.cap) {  // no old residual unless matched below
                 pp.lg.nw.ids[it] = s_id[k];
                 pp.lg.src[it] = -1;
             }
-            if (s_ai[k + 1] == s_ai[k]) {  // no updated cell holds the block: empty item
+            if (s_ro[k + 1] == s_ro[k]) {  // no updated cell holds the block: empty item
                 if (it < D.item_cap) {
                     Item item;
                     item.id = s_id[k];
@@ -473,9 +498,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                     }
                     qn++;
                     if (rows_ok) {
-                        int pos = 0;
-                        for (int w2 = 0; w2 < w; w2++) pos += popc(s_pres[k * WL + w2]);
-                        pos += popc(s_pres[k * WL + w] & ((1u << bit) - 1u));
+                        const int pos = s_cum[k * WL + w] + popc(s_pres[k * WL + w] & ((1u << bit) - 1u));
                         D.rows[rowoff + pos] = (int32_t)((uint32_t)slot | NEWFLAG);
                     }
                 }
@@ -487,7 +510,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         // block of chunk rank k new in cell i is the one the row above took,
         // number s_np[k] + (rank of i among k's new cells) of this chunk's
         // allocation
-        for (int i = wave; i < L; i += 4) {
+        for (int i = wave; i < L; i += PNW) {
             const int want = s_req[i];
             if (want == 0) continue;
             const int have = s_new[i];
@@ -544,7 +567,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
             };
             int32_t nids[4] = {-1, -1, -1, -1}, nsls[4] = {0, 0, 0, 0}, ntid = -1, ntsl = 0;
             if (wave < L) load_rows(wave, nids, nsls, ntid, ntsl);
-            for (int i = wave; i < L; i += 4) {
+            for (int i = wave; i < L; i += PNW) {
                 const int64_t at0 = s_cs[i] + s_pos[i];
                 const int n = s_cc[i];
                 const int iw = i >> 5;
@@ -556,7 +579,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                     sls[k] = nsls[k];
                 }
                 const int32_t tid0 = ntid, tsl0 = ntsl;
-                if (i + 4 < L) load_rows(i + 4, nids, nsls, ntid, ntsl);
+                if (i + PNW < L) load_rows(i + PNW, nids, nsls, ntid, ntsl);
                 for (int e0 = lane; e0 < n; e0 += 256) {
                     if (e0 != lane) {  // lists with more than 256 entries in the chunk
 #pragma unroll
@@ -566,18 +589,30 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                             sls[k] = (e < n) ? D.lslot[at0 + e] : 0;
                         }
                     }
+                    // the four groups' ranks, then their row bases, prefix
+                    // counts and presence words, so the LDS reads overlap (the
+                    // run's blocks lie in the chunk)
+                    int kq[4], ro[4], cm[4];
+                    uint32_t pw[4];
 #pragma unroll
                     for (int kk = 0; kk < 4; kk++) {
                         const int32_t id = ids[kk];
-                        if (id < 0) continue;
-                        const int w = id >> 5;
+                        const int w = id >= 0 ? id >> 5 : 0;
                         const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
-                        if (s_ai[k + 1] == s_ai[k]) continue;
-                        int pos = 0;
-                        for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
-                        pos += popc(s_pres[k * WL + iw] & below);
-                        D.rows[(int64_t)rb + s_ro[k] + pos] = sls[kk];
-                        if (last) __builtin_nontemporal_store((int32_t)(ibp + r0 + k), &D.litem[at0 + e0 + 64 * kk]);
+                        kq[kk] = id >= 0 ? k : 0;
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < 4; kk++) {
+                        ro[kk] = s_ro[kq[kk]];
+                        cm[kk] = s_cum[kq[kk] * WL + iw];
+                        pw[kk] = s_pres[kq[kk] * WL + iw];
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < 4; kk++) {
+                        if (ids[kk] < 0 || cm[kk] == 255) continue;  // no updated cell holds it: no row
+                        D.rows[(int64_t)rb + ro[kk] + cm[kk] + popc(pw[kk] & below)] = sls[kk];
+                        if (last)
+                            __builtin_nontemporal_store((int32_t)(ibp + r0 + kq[kk]), &D.litem[at0 + e0 + 64 * kk]);
                     }
                 }
                 // the tail
@@ -587,17 +622,16 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
                     const int32_t id = pre ? tid0 : D.lid[cs + e];
                     const int w = id >> 5;
                     const int k = s_rank[w] + popc(s_bm[w] & ((1u << (id & 31)) - 1u)) - r0;
-                    if (k < 0 || k >= rn || s_ai[k + 1] == s_ai[k]) continue;
-                    int pos = 0;
-                    for (int w2 = 0; w2 < iw; w2++) pos += popc(s_pres[k * WL + w2]);
-                    pos += popc(s_pres[k * WL + iw] & below);
-                    D.rows[(int64_t)rb + s_ro[k] + pos] = pre ? tsl0 : D.lslot[cs + e];
+                    if (k < 0 || k >= rn) continue;
+                    const int cm = s_cum[k * WL + iw];
+                    if (cm == 255) continue;
+                    D.rows[(int64_t)rb + s_ro[k] + cm + popc(s_pres[k * WL + iw] & below)] = pre ? tsl0 : D.lslot[cs + e];
                     if (last) __builtin_nontemporal_store((int32_t)(ibp + r0 + k), &D.litem[cs + e]);
                 }
             }
         }
         __syncthreads();
-        for (int i = tid; i < L; i += 256) s_pos[i] += s_cc[i];
+        for (int i = tid; i < L; i += PNT) s_pos[i] += s_cc[i];
         __syncthreads();
     }
 
@@ -609,7 +643,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
         const int key = t1 + pp.kstride * t2;
         const int ocnt = pp.lg.old.kcnt[key];
         const int64_t ofirst = pp.lg.old.kfirst[key];
-        for (int j = tid; j < ocnt; j += 256) {
+        for (int j = tid; j < ocnt; j += PNT) {
             const int32_t b = pp.lg.old.ids[ofirst + j];
             const uint32_t w = s_bm[b >> 5];
             if ((w >> (b & 31)) & 1u) {
@@ -620,7 +654,7 @@ __global__ __launch_bounds__(256) void k_plan(Dev D, PlanParams pp)
     }
 
     // commit list growth
-    for (int i = tid; i < L; i += 256) {
+    for (int i = tid; i < L; i += PNT) {
         const int a = s_new[i];
         if (a > 0) D.lcount[base + sd * i] = min(s_cnt[i] + a, s_cap[i]);
     }
@@ -641,7 +675,7 @@ size_t plan_lds_bytes(int W, int R, int WL, int L)
     const size_t lp = (size_t)plan_cells(L);
     size_t b = sizeof(int64_t) * lp * 2 + sizeof(int) * lp * 8;
     b += sizeof(uint32_t) * W + sizeof(int) * (W + 1);
-    b += (size_t)R * WL * 4 * 2 + (size_t)R * 4 + (size_t)(R + 1) * 4 * 3;
+    b += (size_t)R * WL * 4 * 2 + (size_t)R * 4 + (size_t)(R + 1) * 4 * 2 + (size_t)R * WL;
     return b + 64;
 }
 
@@ -677,18 +711,17 @@ void launch_plan(const Dev &D, int d, int sidx, const int lo[3], const int hi[3]
     pp.ulo = lo[d];
     pp.uhi = hi[d];
     pp.dt = dt;
-    // chunk size: keep the workgroup's LDS at <= 34 KiB (plus ~3 KiB static),
-    // so four planner workgroups fit a compute unit's 160 KiB
-    const size_t budget = 34 * 1024;
+    // chunk size: as many block ids as the LDS budget holds
+    const size_t budget = PLAN_LDS_BUDGET;
     size_t fixed = plan_lds_bytes(D.W, 0, pp.WL, pp.L);
-    size_t per = (size_t)pp.WL * 8 + 16;
+    size_t per = (size_t)pp.WL * 9 + 12;
     int R = (fixed < budget) ? (int)((budget - fixed) / per) : 64;
     if (R < 64) R = 64;
     pp.R = R;
     size_t lds = plan_lds_bytes(D.W, R, pp.WL, pp.L);
     int64_t np = (int64_t)pp.n1 * pp.n2;
     if (np <= 0) return;
-    hipLaunchKernelGGL(k_plan, dim3((unsigned)np), dim3(256), lds, st, D, pp);
+    hipLaunchKernelGGL(k_plan, dim3((unsigned)np), dim3(PNT), lds, st, D, pp);
 }
 
 }  // namespace vl
