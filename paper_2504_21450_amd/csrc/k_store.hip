@@ -3,6 +3,7 @@
 // reductions and the FP64 velocity moments.
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "vl_internal.h"
 #include "vl_storage.h"
@@ -344,9 +345,10 @@ void launch_cell_counts(const Dev &D, hipStream_t st)
 // mixture are spread over many wavefronts.  A unit of a cell with one chunk
 // writes the cell's moments; the units of a split cell leave ten partial sums
 // each, which the cell's combine pass adds in chunk order (the same result in
-// every run).  Per block the lanes add f, f c, f c c^T with c the block
-// centre's offset from R (uniform over the block, computed from the two
-// blocks' packed coordinates);
+// every run).  Per block the lanes add f, f k, f k k^T with k the block
+// centre's offset from R in units of 4 dv per axis (uniform over the block,
+// computed from the two blocks' packed coordinates; the units are applied to
+// the sums at the end);
 // each lane's offset o within the block enters once at the end:
 //   sum f (c + o) = S1c + o S0,  sum f (c+o)(c+o)^T = S2c + S1c o^T + o S1c^T + S0 o o^T.
 // ---------------------------------------------------------------------------
@@ -439,10 +441,13 @@ __global__ __launch_bounds__(256) void k_mom_units(Dev D, MomScratch M, double *
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nunits = D.nlocal + (int64_t)min(M.ctr[1], (unsigned long long)M.cap_extra);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
+    // raw storage words, widened when summed (BF16 bits held in 32-bit
+    // registers, which the compiler does not pack in pairs)
     using T = typename Storage<ST>::T;
-    constexpr int NF = ST == VL_F64 ? 8 : 16;  // raw words of NF blocks in flight
-    const T *pool = (const T *)D.pool;
-    const double dvx = D.dv[0], dvy = D.dv[1], dvz = D.dv[2];
+    using RW = typename std::conditional<ST == VL_BF16, uint32_t, T>::type;
+    constexpr int NF = 8;  // blocks per group; two groups are in flight
+    const uint32_t lane_off = (uint32_t)lane * Storage<ST>::BYTES;
+    const uint32_t zslot = (uint32_t)D.trash;  // the all-zero block
     // the lane's velocity offset from its block's centre
     const double o[3] = {((lane & 3) - 1.5) * D.dv[0], (((lane >> 2) & 3) - 1.5) * D.dv[1],
                          ((lane >> 4) - 1.5) * D.dv[2]};
@@ -467,42 +472,79 @@ __global__ __launch_bounds__(256) void k_mom_units(Dev D, MomScratch M, double *
         reference_velocity(D, cnt > 0 ? __builtin_amdgcn_readfirstlane(D.lid[ls + cnt / 2]) : 0, cnt, R, pkR);
         pkR = __builtin_amdgcn_readfirstlane(pkR);
         const int b0 = j * M.chunk, b1 = min(cnt, b0 + M.chunk);
+        // sums with the block centre's offset from R in units of 4 dv per
+        // axis (k, uniform over the block, from the packed coordinates in
+        // scalar registers); the units are applied once per unit below
         double s0 = 0.0, s1[3] = {0.0, 0.0, 0.0}, s2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         auto acc = [&](double f, int32_t pk) {
-            // block centre offset from R, 4 k dv per axis (uniform; k from the
-            // packed block coordinates in scalar registers)
-            const double cx = (double)(4 * ((pk & 1023) - (pkR & 1023))) * dvx;
-            const double cy = (double)(4 * (((pk >> 10) & 1023) - ((pkR >> 10) & 1023))) * dvy;
-            const double cz = (double)(4 * ((pk >> 20) - (pkR >> 20))) * dvz;
-            const double fx = f * cx, fy = f * cy, fz = f * cz;
+            const double kx = (double)((pk & 1023) - (pkR & 1023));
+            const double ky = (double)(((pk >> 10) & 1023) - ((pkR >> 10) & 1023));
+            const double kz = (double)((pk >> 20) - (pkR >> 20));
+            const double fx = f * kx, fy = f * ky, fz = f * kz;
             s0 += f;
             s1[0] += fx;
             s1[1] += fy;
             s1[2] += fz;
-            s2[0] = fma(fx, cx, s2[0]);
-            s2[1] = fma(fy, cy, s2[1]);
-            s2[2] = fma(fz, cz, s2[2]);
-            s2[3] = fma(fx, cy, s2[3]);
-            s2[4] = fma(fx, cz, s2[4]);
-            s2[5] = fma(fy, cz, s2[5]);
+            s2[0] = fma(fx, kx, s2[0]);
+            s2[1] = fma(fy, ky, s2[1]);
+            s2[2] = fma(fz, kz, s2[2]);
+            s2[3] = fma(fx, ky, s2[3]);
+            s2[4] = fma(fx, kz, s2[4]);
+            s2[5] = fma(fy, kz, s2[5]);
         };
         for (int g = b0; g < b1; g += 64) {
+            // slots and packed coordinates of up to 64 blocks, one per lane;
+            // past the list the all-zero block (f = 0 adds nothing)
             const int ng = min(64, b1 - g);
-            const int32_t myid = lane < ng ? D.lid[ls + g + lane] : 0;
-            const int32_t myslot = lane < ng ? D.lslot[ls + g + lane] : 0;
-            const int32_t mypk = pack_coords(D, myid);
-            int k = 0;
-            for (; k + NF <= ng; k += NF) {
-                T r[NF];
+            const uint32_t myslot = lane < ng ? (uint32_t)D.lslot[ls + g + lane] : zslot;
+            const int32_t mypk = lane < ng ? pack_coords(D, D.lid[ls + g + lane]) : pkR;
+            // groups of NF blocks, the next group's loads issued before the
+            // current group is summed (every load is issued: blocks past the
+            // 64 read the all-zero block)
+            RW ra[NF], rb[NF];
+            auto issue = [&](RW (&r)[NF], int k0) {
 #pragma unroll
-                for (int i = 0; i < NF; i++) r[i] = pool[(int64_t)__builtin_amdgcn_readlane(myslot, k + i) * BLK + lane];
+                for (int i = 0; i < NF; i++) {
+                    // (read unconditionally, then chosen: a select, not a branch)
+                    const int k = k0 + i;
+                    const uint32_t rl = (uint32_t)__builtin_amdgcn_readlane((int)myslot, k & 63);
+                    const uint32_t sl = k < 64 ? rl : zslot;
+                    r[i] = block_load_raw<ST>(block_rsrc<ST>(D.pool, sl), lane_off);
+                }
+            };
+            auto take = [&](const RW (&r)[NF], int k0) {
 #pragma unroll
-                for (int i = 0; i < NF; i++) acc(Storage<ST>::widen(r[i]), __builtin_amdgcn_readlane(mypk, k + i));
+                for (int i = 0; i < NF; i++) {
+                    const int k = k0 + i;
+                    const int32_t rl = __builtin_amdgcn_readlane(mypk, k & 63);
+                    acc(Storage<ST>::widen((T)r[i]), k < 64 ? rl : pkR);
+                }
+            };
+            // (scheduling barriers keep each group's loads where they are
+            // issued, ahead of the other group's sums)
+            issue(ra, 0);
+            for (int k0 = 0; k0 < ng; k0 += 2 * NF) {
+                issue(rb, k0 + NF);
+                __builtin_amdgcn_sched_barrier(0);
+                take(ra, k0);
+                __builtin_amdgcn_sched_barrier(0);
+                issue(ra, k0 + 2 * NF);
+                __builtin_amdgcn_sched_barrier(0);
+                take(rb, k0 + NF);
+                __builtin_amdgcn_sched_barrier(0);
             }
-            for (; k < ng; k++)
-                acc(Storage<ST>::widen(pool[(int64_t)__builtin_amdgcn_readlane(myslot, k) * BLK + lane]),
-                    __builtin_amdgcn_readlane(mypk, k));
         }
+        // the block offsets' units (4 dv per axis)
+        const double ux = 4.0 * D.dv[0], uy = 4.0 * D.dv[1], uz = 4.0 * D.dv[2];
+        s1[0] *= ux;
+        s1[1] *= uy;
+        s1[2] *= uz;
+        s2[0] *= ux * ux;
+        s2[1] *= uy * uy;
+        s2[2] *= uz * uz;
+        s2[3] *= ux * uy;
+        s2[4] *= ux * uz;
+        s2[5] *= uy * uz;
         // the lane's offset within its block, then the sums over the lanes
         double S[10];
         S[0] = s0;

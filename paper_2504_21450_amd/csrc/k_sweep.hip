@@ -171,43 +171,9 @@ __device__ __forceinline__ uint16_t narrow_bf16(double x, double &nv)
     return h;
 }
 
-// One block (64 values of one cell) as a buffer resource: the block's address
-// is formed in scalar registers and each lane's value is at byte offset
-// lane * bytes, so no vector instruction computes addresses in the marches.
-// Offsets past the block (none occur) would read zero and drop stores.
-typedef unsigned int vl_u32x2 __attribute__((ext_vector_type(2)));
-constexpr int RSRC_WORD3 = 0x00020000;  // untyped 32-bit buffer access on this architecture
-
-template <int ST>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const Dev &D, uint32_t slot)
-{
-    constexpr int NB = BLK * Storage<ST>::BYTES;
-    return __builtin_amdgcn_make_buffer_rsrc((char *)D.pool + (uint64_t)slot * NB, (short)0, NB, RSRC_WORD3);
-}
-
-template <int ST>
-__device__ __forceinline__ auto block_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
-{
-    if constexpr (ST == VL_F64)
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-    else if constexpr (ST == VL_F32)
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-    else
-        return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
-}
-
-__device__ __forceinline__ void block_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
-{
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(vl_u32x2, v), r, off, 0, 0);
-}
-__device__ __forceinline__ void block_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
-}
-__device__ __forceinline__ void block_store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint16_t v)
-{
-    __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
-}
+// Blocks are read and written through buffer resources made in scalar
+// registers (block_rsrc, block_load, block_store), so no vector instruction
+// computes addresses in the marches.
 
 // One (pencil, block) item: march along the pencil.  DIR = +1 when every
 // lane's Courant number is positive, -1 when every one is negative, 0 when
@@ -359,7 +325,7 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
     auto fetch_raw = [&](uint32_t raw) -> C {
         uint32_t sl = uniform_u32(raw);
         sl = (sl & NEWFLAG) ? zslot : sl;
-        return block_load<ST>(block_rsrc<ST>(D, sl), lane_off);
+        return block_load<ST>(block_rsrc<ST>(D.pool, sl), lane_off);
     };
     auto fetch = [&](int t) -> C { return fetch_raw(srow[t]); };
 
@@ -398,7 +364,7 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
             if (t >= 6 && t < L && t < te) {  // past te: the next segment's march
                 const uint32_t sl3 = uniform_u32(s_raw);
                 if (sl3 != ABSENT) {
-                    const __amdgpu_buffer_rsrc_t dst = block_rsrc<ST>(D, sl3 & ~NEWFLAG);
+                    const __amdgpu_buffer_rsrc_t dst = block_rsrc<ST>(D.pool, sl3 & ~NEWFLAG);
                     double nv;
                     if constexpr (ST == VL_F64) {
                         nv = a3d + (Ff_prev - Ff);

@@ -112,4 +112,53 @@ struct Storage<VL_BF16> {
 
 inline int storage_bytes(int st) { return st == VL_F64 ? 8 : st == VL_F32 ? 4 : 2; }
 
+// One block (64 values of one cell) of the pool as a buffer resource: the
+// block's address is formed in scalar registers and each lane's value is at
+// byte offset lane * bytes, so no vector instruction computes addresses.
+// Offsets past the block (none occur) would read zero and drop stores.
+typedef unsigned int vl_u32x2 __attribute__((ext_vector_type(2)));
+constexpr int RSRC_WORD3 = 0x00020000;  // untyped 32-bit buffer access on this architecture
+
+template <int ST>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(void *pool, uint32_t slot)
+{
+    constexpr int NB = 64 * Storage<ST>::BYTES;
+    return __builtin_amdgcn_make_buffer_rsrc((char *)pool + (uint64_t)slot * NB, (short)0, NB, RSRC_WORD3);
+}
+
+// a lane's value of a block: double for FP64 storage, else float
+template <int ST>
+__device__ __forceinline__ auto block_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    if constexpr (ST == VL_F64)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else if constexpr (ST == VL_F32)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    else
+        return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+
+// a lane's raw storage word of a block (BF16 bits not yet widened)
+template <int ST>
+__device__ __forceinline__ typename Storage<ST>::T block_load_raw(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    if constexpr (ST == VL_BF16)
+        return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    else
+        return block_load<ST>(r, off);
+}
+
+__device__ __forceinline__ void block_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(vl_u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void block_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void block_store(__amdgpu_buffer_rsrc_t r, uint32_t off, uint16_t v)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
+}
+
 }  // namespace vl
