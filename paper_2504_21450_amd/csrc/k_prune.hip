@@ -14,15 +14,18 @@
 //             back to the free ring; created blocks get zeroed slots,
 //   the list is rewritten sorted by block id into the other local list
 //             region, with fresh slack for the next step's growth.
-// The cell's list is staged through LDS in chunks so every global access is
-// coalesced and independent.
+// Every pass over the cell's list takes four entries per thread at a time
+// with their loads issued together; removed blocks are ordered by block id
+// (a prefix count over the bitmap of removed blocks), so each entry finds its
+// place in the new list or in the free ring by itself, and their mass is
+// summed from the slots the workgroup wrote to its part of the ring.
 #include "vl_internal.h"
 #include "vl_storage.h"
 
 namespace vl {
 
-constexpr int PR_CHUNK = 1024;   // list entries staged in LDS at a time
-constexpr int PR_QUEUE = 512;    // removed / created blocks queued for the wavefronts
+constexpr int PR_QUEUE = 512;  // created blocks queued for the wavefronts
+constexpr int PR_UNROLL = 4;   // list entries per thread per pass iteration
 
 __device__ inline int popc32(uint32_t v) { return __popc(v); }
 
@@ -36,20 +39,18 @@ template <int ST>
 __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, double vol)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_tmp[256];
-    __shared__ int32_t s_eid[PR_CHUNK], s_eslot[PR_CHUNK];
+    __shared__ int s_tmp[3][4];
     __shared__ int32_t s_q[PR_QUEUE];
     __shared__ double s_wmass[4];
-    __shared__ unsigned long long s_base[3];
-    __shared__ unsigned long long s_rbase;
+    __shared__ unsigned long long s_base[4];
     __shared__ int s_cnt[4];
-    __shared__ int s_wrem[4];
     __shared__ int s_fail;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int W = D.W;
     uint32_t *s_old = (uint32_t *)smem;
     uint32_t *s_keep = s_old + W;
-    int *s_rank = (int *)(s_keep + W);
+    int *s_rank = (int *)(s_keep + W);   // kept blocks before each word
+    int *s_rrank = s_rank + (W + 1);     // removed blocks before each word
 
     const int64_t q = blockIdx.x;
     const int x = (int)(q % D.n[0]), y = (int)((q / D.n[0]) % D.n[1]), z = (int)(q / ((int64_t)D.n[0] * D.n[1]));
@@ -69,75 +70,113 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
         s_old[w] = 0u;
         s_keep[w] = 0u;
     }
-    if (tid < 4) s_cnt[tid] = 0;
     if (tid == 0) s_fail = failed(D) ? 1 : 0;
     __syncthreads();
     if (s_fail) return;  // fail-stop, one decision per workgroup (nothing written yet)
     // old set and dilated content
-    for (int e = tid; e < cnt; e += 256) {
-        const int32_t id = D.lid[cs + e];
-        const int32_t slot = D.lslot[cs + e];
-        atomicOr(&s_old[id >> 5], 1u << (id & 31));
-        if (accel) {
-            const int fl = D.litem[cs + e];
-            if (!prune) {
-                if (!(fl & 4) || (fl & 2)) atomicOr(&s_keep[id >> 5], 1u << (id & 31));
-                continue;
-            }
-            if (!(fl & 1)) continue;
-        } else {
-            if (!prune) {
-                atomicOr(&s_keep[id >> 5], 1u << (id & 31));
-                continue;
-            }
-            if ((int64_t)slot >= D.lcap) continue;  // scratch slot of a failed allocation
-            const uint32_t it = (uint32_t)D.litem[cs + e];
-            if ((uint64_t)it >= nitems || !(fw[(int64_t)it * D.wlmax] & fbit)) continue;
+    for (int e0 = tid; e0 < cnt; e0 += 256 * PR_UNROLL) {
+        int32_t id[PR_UNROLL], slot[PR_UNROLL], fl[PR_UNROLL];
+        uint32_t word[PR_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PR_UNROLL; u++) {
+            const int e = e0 + 256 * u;
+            const bool v = e < cnt;
+            id[u] = v ? D.lid[cs + e] : -1;
+            slot[u] = v ? D.lslot[cs + e] : 0;
+            fl[u] = (v && (accel || prune)) ? D.litem[cs + e] : 0;
         }
-        const int bx = id % nbx, by = (id / nbx) % nby, bz = id / (nbx * nby);
-        for (int oz = -1; oz <= 1; oz++)
-            for (int oy = -1; oy <= 1; oy++)
-                for (int ox = -1; ox <= 1; ox++) {
-                    const int nz = (ox != 0) + (oy != 0) + (oz != 0);
-                    if (nz > 1 && D.vbuffer != 26) continue;
-                    if (nz == 1 && D.vbuffer == 0) continue;
-                    const int xx = bx + ox, yy = by + oy, zz = bz + oz;
-                    if (xx < 0 || yy < 0 || zz < 0 || xx >= nbx || yy >= nby || zz >= nbz) continue;
-                    const int32_t nid = xx + nbx * (yy + nby * zz);
-                    atomicOr(&s_keep[nid >> 5], 1u << (nid & 31));
+        // the content flag word of each entry's item (last shear)
+#pragma unroll
+        for (int u = 0; u < PR_UNROLL; u++) {
+            const bool need = id[u] >= 0 && !accel && prune && (int64_t)slot[u] < D.lcap && (uint64_t)(uint32_t)fl[u] < nitems;
+            word[u] = need ? fw[(int64_t)(uint32_t)fl[u] * D.wlmax] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < PR_UNROLL; u++) {
+            const int32_t bid = id[u];
+            if (bid < 0) continue;
+            atomicOr(&s_old[bid >> 5], 1u << (bid & 31));
+            bool content;
+            if (accel) {
+                if (!prune) {
+                    if (!(fl[u] & 4) || (fl[u] & 2)) atomicOr(&s_keep[bid >> 5], 1u << (bid & 31));
+                    continue;
                 }
+                content = (fl[u] & 1) != 0;
+            } else {
+                if (!prune) {
+                    atomicOr(&s_keep[bid >> 5], 1u << (bid & 31));
+                    continue;
+                }
+                content = (word[u] & fbit) != 0;  // zero for the scratch slot of a failed allocation
+            }
+            if (!content) continue;
+            const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
+            for (int oz = -1; oz <= 1; oz++)
+                for (int oy = -1; oy <= 1; oy++)
+                    for (int ox = -1; ox <= 1; ox++) {
+                        const int nz = (ox != 0) + (oy != 0) + (oz != 0);
+                        if (nz > 1 && D.vbuffer != 26) continue;
+                        if (nz == 1 && D.vbuffer == 0) continue;
+                        const int xx = bx + ox, yy = by + oy, zz = bz + oz;
+                        if (xx < 0 || yy < 0 || zz < 0 || xx >= nbx || yy >= nby || zz >= nbz) continue;
+                        const int32_t nid = xx + nbx * (yy + nby * zz);
+                        atomicOr(&s_keep[nid >> 5], 1u << (nid & 31));
+                    }
+        }
     }
     __syncthreads();
-    // ranks of the kept blocks (exclusive scan over W words) and counts
-    int ncreate = 0;
+    // kept and removed blocks before each word (exclusive scans: per thread a
+    // run of words, within the wavefront by shuffles, across the wavefronts
+    // through LDS), and the created blocks
     {
         const int per = (W + 255) / 256;
         const int b = min(tid * per, W), e = min(b + per, W);
-        int sum = 0;
+        int sk = 0, sr = 0, sc = 0;
         for (int i = b; i < e; i++) {
-            sum += popc32(s_keep[i]);
-            ncreate += popc32(s_keep[i] & ~s_old[i]);
+            sk += popc32(s_keep[i]);
+            sr += popc32(s_old[i] & ~s_keep[i]);
+            sc += popc32(s_keep[i] & ~s_old[i]);
         }
-        s_tmp[tid] = sum;
+        int ik = sk, ir = sr, ic = sc;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int vk = __shfl_up(ik, o), vr = __shfl_up(ir, o), vc = __shfl_up(ic, o);
+            if (lane >= o) {
+                ik += vk;
+                ir += vr;
+                ic += vc;
+            }
+        }
+        if (lane == 63) {
+            s_tmp[0][wv] = ik;
+            s_tmp[1][wv] = ir;
+            s_tmp[2][wv] = ic;
+        }
         __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {
-            int v = (tid >= o) ? s_tmp[tid - o] : 0;
-            __syncthreads();
-            s_tmp[tid] += v;
-            __syncthreads();
+        int rk = ik - sk, rr = ir - sr;
+        for (int w = 0; w < wv; w++) {
+            rk += s_tmp[0][w];
+            rr += s_tmp[1][w];
         }
-        int run = s_tmp[tid] - sum;
         for (int i = b; i < e; i++) {
-            s_rank[i] = run;
-            run += popc32(s_keep[i]);
+            s_rank[i] = rk;
+            s_rrank[i] = rr;
+            rk += popc32(s_keep[i]);
+            rr += popc32(s_old[i] & ~s_keep[i]);
         }
-        if (tid == 255) s_cnt[0] = s_tmp[255];
+        if (tid == 0) {
+            s_cnt[0] = ((s_tmp[0][0] + s_tmp[0][1]) + s_tmp[0][2]) + s_tmp[0][3];
+            s_cnt[1] = ((s_tmp[2][0] + s_tmp[2][1]) + s_tmp[2][2]) + s_tmp[2][3];
+            s_cnt[2] = ((s_tmp[1][0] + s_tmp[1][1]) + s_tmp[1][2]) + s_tmp[1][3];
+        }
     }
-    atomicAdd(&s_cnt[1], ncreate);
     __syncthreads();
     const int nkeep = s_cnt[0];
     const int ncr = s_cnt[1];
+    const int nrem = s_cnt[2];
     const int cap = nkeep + nkeep / 4 + 32;
+    // the new list's place, the created blocks' slots and the removed blocks'
+    // places in the free ring, one counter update each
     if (tid == 0) {
         unsigned long long err = 0;
         unsigned long long lb = atomicAdd(&D.ctl->list_top[nxt], (unsigned long long)cap);
@@ -146,7 +185,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
             err |= E_LOCAL_LIST;
             ok = 0;
         }
-        unsigned long long rb = 0;
+        unsigned long long rb = 0, tb = 0;
         if (ok && ncr > 0) {
             rb = atomicAdd(&D.ctl->ring_head, (unsigned long long)ncr);
             if (rb + ncr > D.ctl->ring_limit) {
@@ -154,10 +193,12 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
                 ok |= 2;
             }
         }
+        if (ok && nrem > 0) tb = atomicAdd(&D.ctl->ring_tail, (unsigned long long)nrem);
         if (err) atomicOr(&D.ctl->err, err);
         s_base[0] = lb;
-        s_rbase = rb;
+        s_base[1] = tb;
         s_base[2] = ok;
+        s_base[3] = rb;
     }
     __syncthreads();
     if (!(s_base[2] & 1)) {
@@ -165,100 +206,64 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
         return;  // list region full: the cell keeps its old list (error flagged)
     }
     const int64_t ns = D.reg_off[nxt] + (int64_t)s_base[0];
+    const int64_t r0 = (int64_t)(s_base[1] % (unsigned long long)D.lcap);  // the removed blocks' first ring place
+    const unsigned long long rbase = s_base[3];
     const bool ring_failed = (s_base[2] & 2) != 0;
-    double lmass = 0.0;  // this lane's share of the removed blocks of this wavefront
 
-    // old entries: kept ones move to their sorted position, removed ones are
-    // queued (slot) for the mass sum and returned to the ring
-    for (int e0 = 0; e0 < cnt; e0 += PR_CHUNK) {
-        const int m = min(PR_CHUNK, cnt - e0);
-        for (int e = tid; e < m; e += 256) {
-            s_eid[e] = D.lid[cs + e0 + e];
-            s_eslot[e] = D.lslot[cs + e0 + e];
+    // old entries: kept ones to their sorted place in the new list, removed
+    // ones to their place in the free ring (in block-id order)
+    for (int e0 = tid; e0 < cnt; e0 += 256 * PR_UNROLL) {
+        int32_t id[PR_UNROLL], slot[PR_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PR_UNROLL; u++) {
+            const int e = e0 + 256 * u;
+            const bool v = e < cnt;
+            id[u] = v ? D.lid[cs + e] : -1;
+            slot[u] = v ? D.lslot[cs + e] : 0;
         }
-        __syncthreads();
-        // removed entries are queued in entry order (a prefix count over the
-        // workgroup per 256 entries), so their mass is summed in the same order
-        // in every run
-        int nrem_run = 0;
-        for (int r = 0; r < m; r += 256) {
-            const int e = r + tid;
-            bool removed = false;
-            int32_t slot = 0;
-            if (e < m) {
-                const int32_t id = s_eid[e];
-                slot = s_eslot[e];
-                const int w = id >> 5;
-                const uint32_t bit = 1u << (id & 31);
-                if (s_keep[w] & bit) {
-                    const int pos = s_rank[w] + popc32(s_keep[w] & (bit - 1u));
-                    D.lid[ns + pos] = id;
-                    D.lslot[ns + pos] = slot;
-                } else {
-                    removed = true;
-                }
-            }
-            const unsigned long long bal = __ballot(removed);
-            if (lane == 0) s_wrem[wv] = (int)__popcll(bal);
-            __syncthreads();
-            int before = nrem_run;
-            for (int j = 0; j < wv; j++) before += s_wrem[j];
-            const int k = before + (int)__popcll(bal & ((1ull << lane) - 1ull));
-            if (removed) {
-                if (k < PR_QUEUE) s_q[k] = slot;
-                else s_eslot[e] = -1 - slot;  // summed below from the staged entries
-            }
-            nrem_run += ((s_wrem[0] + s_wrem[1]) + s_wrem[2]) + s_wrem[3];
-            __syncthreads();
-        }
-        if (tid == 0) s_cnt[2] = nrem_run;
-        __syncthreads();
-        // return the removed slots to the free ring: one counter update per chunk
-        {
-            const int nrem = s_cnt[2];
-            if (tid == 0 && nrem > 0) s_base[1] = atomicAdd(&D.ctl->ring_tail, (unsigned long long)nrem);
-            __syncthreads();
-            const unsigned long long t0 = s_base[1];
-            for (int k = tid; k < min(nrem, PR_QUEUE); k += 256) {
-                const int32_t slot = s_q[k];
-                D.ring[(int64_t)((t0 + k) % (unsigned long long)D.lcap)] = (int64_t)slot < D.lcap ? slot : (int32_t)D.trash;
-            }
-            if (nrem > PR_QUEUE) {
-                // queue overflow: the remaining removed slots in entry order
-                if (tid == 0) {
-                    int k = PR_QUEUE;
-                    for (int e = 0; e < m; e++) {
-                        const int32_t sl = s_eslot[e];
-                        if (sl < 0) {
-                            const int32_t slot = -1 - sl;
-                            D.ring[(int64_t)((t0 + k) % (unsigned long long)D.lcap)] =
-                                (int64_t)slot < D.lcap ? slot : (int32_t)D.trash;
-                            k++;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        const int nq = min(s_cnt[2], PR_QUEUE);
-        // removed mass: per lane over the wavefront's blocks, four loads in
-        // flight, reduced across the lanes once at the end
-        int k = wv;
-        for (; k + 12 < nq; k += 16) {
-            const double a0 = lane_value<ST>(D, s_q[k], lane), a1 = lane_value<ST>(D, s_q[k + 4], lane);
-            const double a2 = lane_value<ST>(D, s_q[k + 8], lane), a3 = lane_value<ST>(D, s_q[k + 12], lane);
-            lmass += (a0 + a1) + (a2 + a3);
-        }
-        for (; k < nq; k += 4) lmass += lane_value<ST>(D, s_q[k], lane);
-        if (s_cnt[2] > PR_QUEUE) {
-            // overflow of the queue: sum the rest entry by entry
-            for (int e = wv; e < m; e += 4) {
-                const int32_t sl = s_eslot[e];
-                if (sl < 0) lmass += lane_value<ST>(D, -1 - sl, lane);
+#pragma unroll
+        for (int u = 0; u < PR_UNROLL; u++) {
+            const int32_t bid = id[u];
+            if (bid < 0) continue;
+            const int w = bid >> 5;
+            const uint32_t bit = 1u << (bid & 31), below = bit - 1u;
+            const uint32_t kw = s_keep[w];
+            if (kw & bit) {
+                const int pos = s_rank[w] + popc32(kw & below);
+                D.lid[ns + pos] = bid;
+                D.lslot[ns + pos] = slot[u];
+            } else {
+                const int k = s_rrank[w] + popc32(s_old[w] & ~kw & below);
+                int64_t r = r0 + k;  // k < nrem <= lcap
+                if (r >= D.lcap) r -= D.lcap;
+                D.ring[r] = (int64_t)slot[u] < D.lcap ? slot[u] : (int32_t)D.trash;
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
+    // removed mass: each wavefront takes 64 removed blocks at a time, their
+    // slots read back from the workgroup's places in the ring (one coalesced
+    // vector load; written above by this workgroup), the blocks summed per
+    // lane with eight loads in flight; reduced across the lanes at the end
+    double lmass = 0.0;
+    for (int k0 = 64 * wv; k0 < nrem; k0 += 256) {
+        const int n = min(64, nrem - k0);
+        int32_t myslot = (int32_t)D.trash;
+        if (lane < n) {
+            int64_t r = r0 + k0 + lane;
+            if (r >= D.lcap) r -= D.lcap;
+            myslot = D.ring[r];
+        }
+        int j = 0;
+        for (; j + 8 <= n; j += 8) {
+            double a[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) a[i] = lane_value<ST>(D, __builtin_amdgcn_readlane(myslot, j + i), lane);
+            lmass += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        }
+        for (; j < n; j++) lmass += lane_value<ST>(D, __builtin_amdgcn_readlane(myslot, j), lane);
+    }
+    __syncthreads();
     // created blocks: take slots, record them, zero them
     if (ncr > 0) {
         if (tid == 0) s_cnt[3] = 0;
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
                 const int pos = s_rank[w] + popc32(s_keep[w] & ((1u << bit) - 1u));
                 const int ci = atomicAdd(&s_cnt[3], 1);
                 const int64_t slot = ring_failed ? D.trash
-                                                 : (int64_t)D.ring[(int64_t)((s_rbase + ci) % (unsigned long long)D.lcap)];
+                                                 : (int64_t)D.ring[(int64_t)((rbase + ci) % (unsigned long long)D.lcap)];
                 D.lid[ns + pos] = id;
                 D.lslot[ns + pos] = (int32_t)slot;
                 if (ci < PR_QUEUE) {
@@ -303,7 +308,7 @@ __global__ __launch_bounds__(256) void k_prune(Dev D, int nxt, int last_axis, do
 
 void launch_prune(const Dev &D, int nxt, int last_axis, hipStream_t st)
 {
-    size_t lds = sizeof(uint32_t) * D.W * 2 + sizeof(int) * (D.W + 1) + 64;
+    size_t lds = sizeof(uint32_t) * D.W * 2 + sizeof(int) * (D.W + 1) * 2 + 64;
     const double vol = D.dx[0] * D.dx[1] * D.dx[2] * D.dv[0] * D.dv[1] * D.dv[2];
     dim3 g((unsigned)D.nlocal), b(256);
     switch (D.storage) {
