@@ -307,12 +307,14 @@ __device__ __forceinline__ void march_unc(const Dev &D, const uint32_t *srow, ui
 
 
 // Variant "conditional stores": the slot of each cell is read from LDS when
-// needed and the store is skipped (scalar branch) for cells without the block
-// and outside the updated range; prefetch distance PFV cells.
+// it is fetched (prefetch distance PFV) and kept in scalar registers until
+// the cell is written PFV + 3 iterations later; the store is skipped (scalar
+// branch) for cells without the block and outside the updated range.
 template <int ST, int DIR, bool LAST, int PFV>
 __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, uint8_t *sflag, int L, double c,
                                            int lane, double smin, double &carry, int tb, int te)
 {
+    static_assert(PFV >= 3, "the written cell's slot comes from the previous group");
     using C = typename std::conditional<ST == VL_F64, double, float>::type;  // reconstruction type
     const bool pos = (DIR > 0) ? true : (DIR < 0) ? false : (c > 0.0);
     const double s = fabs(c);
@@ -322,12 +324,11 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
     const uint32_t lane_off = (uint32_t)lane * BS;
     const uint32_t zslot = (uint32_t)D.trash;
 
-    auto fetch_raw = [&](uint32_t raw) -> C {
-        uint32_t sl = uniform_u32(raw);
-        sl = (sl & NEWFLAG) ? zslot : sl;
-        return block_load<ST>(block_rsrc<ST>(D.pool, sl), lane_off);
+    // a cell's value from its raw slot (wave-uniform): absent or created this
+    // shear reads the all-zero block
+    auto fetch_raw = [&](uint32_t sl) -> C {
+        return block_load<ST>(block_rsrc<ST>(D.pool, (sl & NEWFLAG) ? zslot : sl), lane_off);
     };
-    auto fetch = [&](int t) -> C { return fetch_raw(srow[t]); };
 
     C a1 = 0, a2 = 0;
     double a3d = 0.0;
@@ -335,22 +336,29 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
     C face_prev = 0;
     double Fc_prev = 0.0, Ff_prev = 0.0;
     C q[PFV];
+    // raw slots of the cells t0 .. t0+PFV-1 (fetched by the previous group or
+    // the prologue), of the three cells before them, and of the cells this
+    // group fetches
+    uint32_t prv[PFV], bef[3], cur[PFV];
 #pragma unroll
-    for (int u = 0; u < PFV; u++) q[u] = fetch(tb + u);
-    // slot-table entries of the cell fetched and the cell stored by the next
-    // iteration, read from LDS one iteration ahead so their latency is hidden
-    // behind a cell's arithmetic (the table is padded with ABSENT past L)
+    for (int u = 0; u < PFV; u++) {
+        prv[u] = uniform_u32(srow[tb + u]);
+        q[u] = fetch_raw(prv[u]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; i++) bef[i] = (tb - 3 + i >= 0) ? uniform_u32(srow[tb - 3 + i]) : ABSENT;
+    // the slot-table entry of the next iteration's fetch, read from LDS one
+    // iteration ahead so its latency is hidden behind a cell's arithmetic
+    // (the table is padded with ABSENT past L)
     uint32_t f_next = srow[tb + PFV];
-    uint32_t s_next = srow[tb >= 3 ? tb - 3 : 0];
     for (int t0 = tb; t0 < te; t0 += PFV) {
 #pragma unroll
         for (int u = 0; u < PFV; u++) {
             const int t = t0 + u;
-            const uint32_t f_raw = f_next, s_raw = s_next;
+            cur[u] = uniform_u32(f_next);
             f_next = srow[t + PFV + 1];
-            s_next = srow[t >= 2 ? t - 2 : 0];
             const C a = q[u];
-            q[u] = fetch_raw(f_raw);
+            q[u] = fetch_raw(cur[u]);
             const C dl = a1 - a2, dr = a - a1;
             const C cen = (C)0.5 * (a - a2);
             const C da = limited_slope(dl, dr, cen);
@@ -362,7 +370,7 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
             const double Fc = fma(P, dRp, fma(Q, dLp, c * aid));
             const double Ff = (DIR > 0) ? Fc_prev : (DIR < 0) ? Fc : (pos ? Fc_prev : Fc);
             if (t >= 6 && t < L && t < te) {  // past te: the next segment's march
-                const uint32_t sl3 = uniform_u32(s_raw);
+                const uint32_t sl3 = (u >= 3) ? prv[u - 3] : bef[u];  // cell t - 3
                 if (sl3 != ABSENT) {
                     const __amdgpu_buffer_rsrc_t dst = block_rsrc<ST>(D.pool, sl3 & ~NEWFLAG);
                     double nv;
@@ -394,6 +402,10 @@ __device__ __forceinline__ void march_cond(const Dev &D, const uint32_t *srow, u
             Fc_prev = Fc;
             Ff_prev = Ff;
         }
+#pragma unroll
+        for (int i = 0; i < 3; i++) bef[i] = prv[PFV - 3 + i];
+#pragma unroll
+        for (int u = 0; u < PFV; u++) prv[u] = cur[u];
     }
 }
 
