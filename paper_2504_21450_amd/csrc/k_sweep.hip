@@ -486,7 +486,6 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int d = sp.d, L = sp.L, WL = sp.WL;
-    const int ld = (d == 0) ? (lane & 3) : (d == 1) ? ((lane >> 2) & 3) : (lane >> 4);
     const int64_t nitems = min((int64_t)D.ctl->n_items, D.item_cap);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     uint32_t *srow = s_slot[wv];
@@ -494,6 +493,12 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
 
     for (int64_t it = (int64_t)blockIdx.x * 4 + wv; it < nitems; it += nwaves) {
         const Item item = D.items[it];
+        // the lane index as a value of this item (an empty asm the compiler
+        // cannot see through), so the per-lane index arithmetic of the slot
+        // table below is recomputed per item rather than hoisted out of the
+        // loop and kept in registers, which spill at eight waves per SIMD
+        int li = lane;
+        __asm__ volatile("" : "+v"(li));
         // presence of the block along the pencil (wave-uniform), and the
         // starts of gaps of at least 6 cells without it
         uint32_t m[MAXWL], gap[MAXWL];
@@ -520,7 +525,7 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
                 for (int k = 1; k < 6; k++) r &= (a0 >> k) | (a1 << (32 - k));
                 gap[w] = r & ((m[w] << 1) | (w > 0 ? m[w - 1] >> 31 : 0u));
             }
-            const int half = lane >> 5, b = lane & 31;
+            const int half = li >> 5, b = li & 31;
 #pragma unroll
             for (int w = 0; w < MAXWL; w += 2) {
                 if (w < WL) {
@@ -534,11 +539,17 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
                     }
                 }
             }
-            for (int t = L + lane; t < L + 40; t += 64) srow[t] = ABSENT;
+            for (int t = L + li; t < L + 40; t += 64) srow[t] = ABSENT;
         }
         wave_sync_lds();
 
-        const int bd = block_coord(D, d, item.id);
+        // the block's coordinate along d (the mesh extents passed through an
+        // empty asm, so the divisions' reciprocals are formed per item, not
+        // kept in registers across items) and the lane's velocity cell in it
+        int nb0 = D.nblk[0], nb1 = D.nblk[1];
+        __asm__ volatile("" : "+s"(nb0), "+s"(nb1));
+        const int bd = (d == 0) ? item.id % nb0 : (d == 1) ? (item.id / nb0) % nb1 : item.id / (nb0 * nb1);
+        const int ld = (d == 0) ? (li & 3) : (d == 1) ? ((li >> 2) & 3) : (li >> 4);
         const double c = courant(D, d, 4 * bd + ld, sp.dt);
         const unsigned long long npos = __ballot(c > 0.0), nneg = __ballot(c < 0.0);
         double start_sum;
