@@ -321,8 +321,10 @@ int vl_profile_stop(vl_partition *p, double *ms, int64_t *launches);
  * shear kernel (store scheme, prefetch depth, occupancy target), then rounds
  * over the variants within 25 % of the best mean time on some shear, until
  * the steps are spent.  Each shear launch is timed with HIP events on the
- * partition's stream; for each of the three shears of the order the variant
- * with the lowest mean time on it is kept (the third shear, which also
+ * partition's stream and taken per phase-space cell the shear read and
+ * updated (the lists grow from step to step, and the variants tried first
+ * would otherwise look faster); for each of the three shears of the order
+ * the variant with the lowest mean of that time on it is kept (the third shear, which also
  * records the blocks' content flags, has kernels of its own with other
  * register needs).  All variants compute bit-identical results, so the state
  * advances exactly as with ordinary steps.  best[3] receives the chosen

@@ -991,6 +991,9 @@ int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_vari
     const int nv = sweep_variants();
     const int budget = steps_per_variant * nv;      // real steps in all
     std::vector<double> t((size_t)nv * 4, 0.0);     // per variant: summed ms of shears 1..3, all
+    // per variant and shear: summed ms per 1e9 phase-space cells the shear
+    // read and updated, so steps taken as the lists grow compare alike
+    std::vector<double> r((size_t)nv * 3, 0.0);
     std::vector<int> k((size_t)nv, 0);              // steps run with each variant
     auto run = [&](int v) -> int {
         for (int s = 0; s < 3; s++) p->D.sweep_variant[s] = v;
@@ -1007,15 +1010,23 @@ int vl_autotune(vl_partition *p, double dt, int32_t mode, int32_t steps_per_vari
         double ms[K_NCLS];
         int64_t n[K_NCLS];
         if ((rc = vl_profile_stop(p, ms, n))) return rc;
-        for (int s = 0; s < 3; s++) t[(size_t)v * 4 + s] += ms[K_SHEAR0 + s];
+        Ctl ctl;
+        VL_HIP(hipMemcpyAsync(&ctl, p->D.ctl, sizeof(ctl), hipMemcpyDeviceToHost, p->stream));
+        VL_HIP(hipStreamSynchronize(p->stream));
+        for (int s = 0; s < 3; s++) {
+            t[(size_t)v * 4 + s] += ms[K_SHEAR0 + s];
+            const double cells = (double)(ctl.upd_ps[s] + ctl.read_ps[s]);
+            r[(size_t)v * 3 + s] += ms[K_SHEAR0 + s] * 1e9 / std::max(cells, 1.0);
+        }
         t[(size_t)v * 4 + 3] += ms[K_SWEEP];
         k[v]++;
         return VL_OK;
     };
-    auto mean = [&](int v, int s) { return t[(size_t)v * 4 + s] / k[v]; };
+    auto mean = [&](int v, int s) { return r[(size_t)v * 3 + s] / k[v]; };
     // One step with every variant, then rounds over the variants within 25 %
-    // of the best mean on some shear until the steps are spent; rounds keep
-    // the slow growth of the state weighing on the compared variants alike.
+    // of the best mean on some shear until the steps are spent; each shear's
+    // time is taken per cell it read and updated, so the growth of the lists
+    // from step to step does not favour the variants tried first.
     int done = 0, rc;
     for (int v = 0; v < nv; v++, done++)
         if ((rc = run(v))) return rc;
