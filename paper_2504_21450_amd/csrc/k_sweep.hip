@@ -87,8 +87,8 @@ __device__ __forceinline__ double take_residual(const SweepParams &sp, int64_t i
             if (s >= 0) r = uniform_f64(sp.lg_old[s]);
         }
     }
-    sum = r;
-    return r * (1.0 / BLK);
+    sum = uniform_f64(r);  // kept in scalar registers for the whole item
+    return sum * (1.0 / BLK);
 }
 
 // Leave the line's final carry, summed over the lanes in a fixed order, for
@@ -514,7 +514,7 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
             if (pre[MAXWL] == 0) {  // empty item: no updated cell, the residual passes on
                 double sum;
                 const double r = take_residual<ST>(sp, it, sum);
-                leave_residual<ST>(D, sp, it, lane, r, sum);
+                leave_residual<ST>(D, sp, it, li, r, sum);
                 continue;
             }
 #pragma unroll
@@ -566,7 +566,7 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
         for (int tb = first_bit(m, 0); tb >= 0;) {
             const int g = first_bit(gap, tb + 1);
             const int te = (g >= 0) ? g + 3 : last_bit(m) + 4;
-            if (lane == 0) sseg[nseg] = (uint32_t)tb | ((uint32_t)te << 16);
+            if (li == 0) sseg[nseg] = (uint32_t)tb | ((uint32_t)te << 16);
             nseg++;
             tb = (g >= 0) ? first_bit(m, g) : -1;
         }
@@ -575,19 +575,19 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
             const uint32_t v = uniform_u32(sseg[k]);
             const int tb = (int)(v & 0xffffu), te = (int)(v >> 16);
             if (npos == ~0ull)
-                march<ST, 1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
+                march<ST, 1, LAST, V>(D, srow, sflag, L, c, li, sp.sparse_min, carry, tb, te);
             else if (nneg == ~0ull)
-                march<ST, -1, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
+                march<ST, -1, LAST, V>(D, srow, sflag, L, c, li, sp.sparse_min, carry, tb, te);
             else
-                march<ST, 0, LAST, V>(D, srow, sflag, L, c, lane, sp.sparse_min, carry, tb, te);
+                march<ST, 0, LAST, V>(D, srow, sflag, L, c, li, sp.sparse_min, carry, tb, te);
         }
         if constexpr (LAST) {
             wave_sync_lds();
-            store_flag_words(D, it, srow, sflag, L, lane);
+            store_flag_words(D, it, srow, sflag, L, li);
         }
 
         // the line's final carry (the ledger takes those of the local pencils)
-        leave_residual<ST>(D, sp, it, lane, carry, start_sum);
+        leave_residual<ST>(D, sp, it, li, carry, start_sum);
         wave_sync_lds();
     }
 }
