@@ -493,12 +493,13 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
 
     for (int64_t it = (int64_t)blockIdx.x * 4 + wv; it < nitems; it += nwaves) {
         const Item item = D.items[it];
-        // the lane index as a value of this item (an empty asm the compiler
-        // cannot see through), so the per-lane index arithmetic of the slot
-        // table below is recomputed per item rather than hoisted out of the
-        // loop and kept in registers, which spill at eight waves per SIMD
-        int li = lane;
-        __asm__ volatile("" : "+v"(li));
+        // the lane index and the mask words as values of this item (an empty
+        // asm the compiler cannot see through), so the per-lane index
+        // arithmetic and the word tests of the slot table below are
+        // recomputed per item rather than hoisted out of the loop and kept in
+        // registers, which spill at eight waves per SIMD
+        int li = lane, wl = WL;
+        __asm__ volatile("" : "+v"(li), "+s"(wl));
         // presence of the block along the pencil (wave-uniform), and the
         // starts of gaps of at least 6 cells without it
         uint32_t m[MAXWL], gap[MAXWL];
@@ -508,7 +509,7 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
             pre[0] = 0;
 #pragma unroll
             for (int w = 0; w < MAXWL; w++) {
-                m[w] = (w < WL) ? __builtin_amdgcn_readfirstlane(D.masks[it * D.wlmax + w]) : 0u;
+                m[w] = (w < wl) ? __builtin_amdgcn_readfirstlane(D.masks[it * D.wlmax + w]) : 0u;
                 pre[w + 1] = pre[w] + __popc(m[w]);
             }
             if (pre[MAXWL] == 0) {  // empty item: no updated cell, the residual passes on
@@ -528,7 +529,7 @@ __device__ __forceinline__ void sweep_body(const Dev &D, const SweepParams &sp)
             const int half = li >> 5, b = li & 31;
 #pragma unroll
             for (int w = 0; w < MAXWL; w += 2) {
-                if (w < WL) {
+                if (w < wl) {
                     const uint32_t mw = half ? m[w + 1] : m[w];
                     const int base = half ? pre[w + 1] : pre[w];
                     const int t = 32 * (w + half) + b;
